@@ -85,6 +85,8 @@ def _load():
         lib.ora_p2m_transpose.argtypes = [_dp, _dp, _i32p, _int, _int, _dp, _dp, _dp]
         lib.ora_direct.argtypes = [_dp, _dp, _i64, _dp, _i64, _dp, _dp]
         lib.ora_direct_grad.argtypes = [_dp, _dp, _i64, _dp, _i64, _dp, _dp, _dp]
+        lib.ora_num_threads.restype = _int
+        lib.ora_num_threads.argtypes = []
         lib.ora_init()
         _lib = lib
         return lib
@@ -112,6 +114,11 @@ def _c128(a):
 
 
 # ------------------------------------------------------------------ tree ---
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().ora_num_threads())
+
 
 def num_boxes(depth: int) -> int:
     return int(_load().ora_num_boxes(depth))

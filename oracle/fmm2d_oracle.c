@@ -149,6 +149,14 @@ static double binom(int a, int b) { return binom_tab[a][b]; }
 
 void ora_init(void) { binom_init(); }
 
+/* Number of OpenMP threads the parallel loops use (1 without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+int ora_num_threads(void) { return omp_get_max_threads(); }
+#else
+int ora_num_threads(void) { return 1; }
+#endif
+
 /* ------------------------------------------------------- upward sweep --- */
 
 /*

@@ -1,0 +1,295 @@
+"""ctypes binding of libfmm2d.so: the C ABI of include/fmm2d.h on torch tensors.
+
+Every function here only marshals arguments (device pointers of contiguous
+tensors, sizes, the current HIP stream) and allocates outputs with torch; all
+arithmetic runs in the library's HIP kernels.  A missing or unloadable library
+raises immediately: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfmm2d.so")
+
+F32, BF16X3, F16X3 = 0, 1, 2
+PRECISIONS = {"f32": F32, "bf16x3": BF16X3, "f16x3": F16X3}
+
+_lock = threading.Lock()
+_lib = None
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+_sz = ctypes.c_size_t
+
+# name -> (restype, argtypes); mirrors include/fmm2d.h
+_SIGNATURES = {
+    "fmm2d_abi_version": (_int, []),
+    "fmm2d_last_error": (ctypes.c_char_p, []),
+    "fmm2d_num_boxes": (_i64, [_int]),
+    "fmm2d_level_offset": (_i64, [_int]),
+    "fmm2d_translation_count": (_i64, [_int, _int]),
+    "fmm2d_build_tree_workspace": (_sz, [_i64, _int]),
+    "fmm2d_build_tree": (_int, [_vp, _i64, _int, _vp, _vp, _vp, _sz, _vp]),
+    "fmm2d_gather": (_int, [_vp, _vp, _i64, _int, _vp, _vp]),
+    "fmm2d_scatter": (_int, [_vp, _vp, _i64, _int, _vp, _vp]),
+    "fmm2d_p2m": (_int, [_vp, _vp, _vp, _int, _int, _vp, _vp]),
+    "fmm2d_m2m": (_int, [_vp, _int, _int, _vp]),
+    "fmm2d_m2l_operators_bytes": (_sz, [_int, _int]),
+    "fmm2d_m2l_operators": (_int, [_int, _int, _vp, _sz, _vp]),
+    "fmm2d_m2l": (_int, [_vp, _vp, _vp, _int, _int, _int, _int, _int, _vp, _sz, _vp]),
+    "fmm2d_m2l_backward": (_int, [_vp, _vp, _vp, _int, _int, _int, _int, _int, _vp, _sz, _vp]),
+    "fmm2d_l2l": (_int, [_vp, _vp, _vp, _vp, _int, _int, _vp]),
+    "fmm2d_l2p": (_int, [_vp, _vp, _i64, _vp, _vp, _int, _int, _vp, _vp, _vp]),
+    "fmm2d_p2p": (_int, [_vp, _vp, _vp, _vp, _vp, _i64, _int, _vp, _vp, _vp]),
+    "fmm2d_l2p_backward": (_int, [_vp, _vp, _vp, _vp, _int, _int, _vp, _vp, _vp]),
+    "fmm2d_l2l_backward": (_int, [_vp, _vp, _vp, _vp, _int, _int, _vp]),
+    "fmm2d_m2m_backward": (_int, [_vp, _int, _int, _vp]),
+    "fmm2d_p2m_backward": (_int, [_vp, _vp, _vp, _i64, _int, _int, _vp, _vp, _vp, _vp]),
+    "fmm2d_p2p_backward": (_int, [_vp, _vp, _vp, _i64, _vp, _vp, _int, _vp, _vp, _vp, _vp, _vp]),
+}
+
+
+def load():
+    """Load libfmm2d.so (raises OSError if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise OSError(f"{LIB_PATH} is missing: run paper_1009_3457_amd.build.build() first")
+            lib = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in _SIGNATURES.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+        return _lib
+
+
+class FMMError(RuntimeError):
+    pass
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = load().fmm2d_last_error().decode()
+        raise FMMError(f"libfmm2d status {rc}: {msg}")
+
+
+def _p(t):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return _vp(t.data_ptr())
+
+
+def _stream(device=None):
+    return _vp(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev(t):
+    if not t.is_cuda:
+        raise ValueError("tensor must be on a GPU device")
+    return t.device
+
+
+# ------------------------------------------------------------ queries ---
+
+def num_boxes(depth: int) -> int:
+    return int(load().fmm2d_num_boxes(depth))
+
+
+def level_offset(level: int) -> int:
+    return int(load().fmm2d_level_offset(level))
+
+
+def translation_count(lmin: int, lmax: int) -> int:
+    return int(load().fmm2d_translation_count(lmin, lmax))
+
+
+# ---------------------------------------------------------------- tree ---
+
+def build_tree(xy: torch.Tensor, depth: int):
+    """Stable leaf sort: returns (perm [n] int32, leaf_start [4^depth+1] int32)."""
+    dev = _dev(xy)
+    n = xy.shape[0]
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    ls = torch.empty((1 << (2 * depth)) + 1, dtype=torch.int32, device=dev)
+    wsb = int(load().fmm2d_build_tree_workspace(n, depth))
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    _check(load().fmm2d_build_tree(_p(xy), n, depth, _p(perm), _p(ls), _p(ws), wsb, _stream(dev)))
+    return perm, ls
+
+
+def _row_width(src: torch.Tensor) -> int:
+    if src.dtype not in (torch.float32, torch.complex64):
+        raise ValueError("gather/scatter move float32 or complex64 rows")
+    per_row = src.numel() // max(src.shape[0], 1)
+    return per_row * (2 if src.is_complex() else 1)
+
+
+def gather(src: torch.Tensor, perm: torch.Tensor) -> torch.Tensor:
+    """dst[i] = src[perm[i]] for float32 / complex64 rows."""
+    n = perm.shape[0]
+    width = _row_width(src)
+    dst = torch.empty_like(src)
+    _check(load().fmm2d_gather(_p(src), _p(perm), n, width, _p(dst), _stream(_dev(src))))
+    return dst
+
+
+def scatter(src: torch.Tensor, perm: torch.Tensor) -> torch.Tensor:
+    """dst[perm[i]] = src[i] for float32 / complex64 rows."""
+    n = perm.shape[0]
+    width = _row_width(src)
+    dst = torch.empty_like(src)
+    _check(load().fmm2d_scatter(_p(src), _p(perm), n, width, _p(dst), _stream(_dev(src))))
+    return dst
+
+
+# -------------------------------------------------------- upward sweep ---
+
+def p2m(xy_sorted, q_sorted, leaf_start, depth: int, p: int, M=None):
+    dev = _dev(xy_sorted)
+    if M is None:
+        M = torch.zeros(num_boxes(depth), p, dtype=torch.complex64, device=dev)
+    _check(load().fmm2d_p2m(_p(xy_sorted), _p(q_sorted), _p(leaf_start), depth, p, _p(M), _stream(dev)))
+    return M
+
+
+def m2m(M, depth: int, p: int):
+    _check(load().fmm2d_m2m(_p(M), depth, p, _stream(_dev(M))))
+    return M
+
+
+# ------------------------------------------------------ downward sweep ---
+
+_ops_cache = {}
+
+
+def m2l_operators(p: int, precision: int, device) -> torch.Tensor:
+    """The operator bank for (p, precision) on `device` (generated once)."""
+    device = torch.device(device)
+    key = (device.index, p, precision)
+    ops = _ops_cache.get(key)
+    if ops is None:
+        nbytes = int(load().fmm2d_m2l_operators_bytes(p, precision))
+        if nbytes == 0:
+            raise FMMError(f"no operator bank for p={p}, precision={precision}")
+        ops = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        _check(load().fmm2d_m2l_operators(p, precision, _p(ops), nbytes, _stream(device)))
+        _ops_cache[key] = ops
+    return ops
+
+
+def m2l(M, depth: int, p: int, lmin: int = 2, lmax: int | None = None, precision: int = F32,
+        L=None, b=None, with_b: bool = True, ops=None):
+    """M2L + reduction on levels lmin..lmax; returns (L, b) (b None if not with_b)."""
+    dev = _dev(M)
+    lmax = depth if lmax is None else lmax
+    nb = num_boxes(depth)
+    if L is None:
+        L = torch.zeros(nb, p, dtype=torch.complex64, device=dev)
+    if b is None and with_b:
+        b = torch.zeros(nb, dtype=torch.complex64, device=dev)
+    ops = m2l_operators(p, precision, dev) if ops is None else ops
+    _check(load().fmm2d_m2l(_p(M), _p(L), _p(b), depth, p, lmin, lmax, precision, _p(ops), ops.numel(),
+                            _stream(dev)))
+    return L, b
+
+
+def m2l_backward(gL, gb, depth: int, p: int, lmin: int = 2, lmax: int | None = None,
+                 precision: int = F32, gM=None, ops=None):
+    """Plain transpose of m2l; returns gM (levels lmin..lmax written)."""
+    dev = _dev(gL)
+    lmax = depth if lmax is None else lmax
+    if gM is None:
+        gM = torch.zeros(num_boxes(depth), p, dtype=torch.complex64, device=dev)
+    ops = m2l_operators(p, precision, dev) if ops is None else ops
+    _check(load().fmm2d_m2l_backward(_p(gL), _p(gb), _p(gM), depth, p, lmin, lmax, precision, _p(ops),
+                                     ops.numel(), _stream(dev)))
+    return gM
+
+
+def l2l(Lm2l, bm2l, depth: int, p: int):
+    dev = _dev(Lm2l)
+    nb = num_boxes(depth)
+    L = torch.empty(nb, p, dtype=torch.complex128, device=dev)
+    b = None if bm2l is None else torch.empty(nb, dtype=torch.complex128, device=dev)
+    _check(load().fmm2d_l2l(_p(Lm2l), _p(bm2l), _p(L), _p(b), depth, p, _stream(dev)))
+    return L, b
+
+
+def l2p(txy_sorted, tleaf_start, L, b, depth: int, p: int, phi=None, field=None):
+    dev = _dev(L)
+    nt = txy_sorted.shape[0]
+    if phi is None:
+        phi = torch.zeros(nt, dtype=torch.complex64, device=dev)
+    if field is None:
+        field = torch.zeros(nt, dtype=torch.complex64, device=dev)
+    _check(load().fmm2d_l2p(_p(txy_sorted), _p(tleaf_start), nt, _p(L), _p(b), depth, p, _p(phi),
+                            _p(field), _stream(dev)))
+    return phi, field
+
+
+def p2p(xy_sorted, q_sorted, leaf_start, txy_sorted, tleaf_start, depth: int, phi=None, field=None):
+    dev = _dev(xy_sorted)
+    nt = txy_sorted.shape[0]
+    if phi is None:
+        phi = torch.zeros(nt, dtype=torch.complex64, device=dev)
+    if field is None:
+        field = torch.zeros(nt, dtype=torch.complex64, device=dev)
+    _check(load().fmm2d_p2p(_p(xy_sorted), _p(q_sorted), _p(leaf_start), _p(txy_sorted),
+                            _p(tleaf_start), nt, depth, _p(phi), _p(field), _stream(dev)))
+    return phi, field
+
+
+# ---------------------------------------------------------- transposes ---
+
+def l2p_backward(txy_sorted, tleaf_start, cphi, cfield, depth: int, p: int):
+    dev = _dev(txy_sorted)
+    nb = num_boxes(depth)
+    gL = torch.zeros(nb, p, dtype=torch.complex128, device=dev)
+    gb = torch.zeros(nb, dtype=torch.complex128, device=dev)
+    _check(load().fmm2d_l2p_backward(_p(txy_sorted), _p(tleaf_start), _p(cphi), _p(cfield), depth, p,
+                                     _p(gL), _p(gb), _stream(dev)))
+    return gL, gb
+
+
+def l2l_backward(gL, gb, depth: int, p: int):
+    dev = _dev(gL)
+    nb = num_boxes(depth)
+    gLm = torch.zeros(nb, p, dtype=torch.complex64, device=dev)
+    gbm = None if gb is None else torch.zeros(nb, dtype=torch.complex64, device=dev)
+    _check(load().fmm2d_l2l_backward(_p(gL), _p(gb), _p(gLm), _p(gbm), depth, p, _stream(dev)))
+    return gLm, gbm
+
+
+def m2m_backward(gM, depth: int, p: int):
+    _check(load().fmm2d_m2m_backward(_p(gM), depth, p, _stream(_dev(gM))))
+    return gM
+
+
+def p2m_backward(xy_sorted, q_sorted, leaf_start, depth: int, p: int, gM):
+    dev = _dev(xy_sorted)
+    n = xy_sorted.shape[0]
+    gq = torch.empty(n, dtype=torch.float32, device=dev)
+    G = torch.empty(n, dtype=torch.complex64, device=dev)
+    _check(load().fmm2d_p2m_backward(_p(xy_sorted), _p(q_sorted), _p(leaf_start), n, depth, p, _p(gM),
+                                     _p(gq), _p(G), _stream(dev)))
+    return gq, G
+
+
+def p2p_backward(xy_sorted, q_sorted, leaf_start, txy_sorted, tleaf_start, depth: int, cphi, cfield,
+                 gq, G):
+    dev = _dev(xy_sorted)
+    n = xy_sorted.shape[0]
+    _check(load().fmm2d_p2p_backward(_p(xy_sorted), _p(q_sorted), _p(leaf_start), n, _p(txy_sorted),
+                                     _p(tleaf_start), depth, _p(cphi), _p(cfield), _p(gq), _p(G),
+                                     _stream(dev)))
+    return gq, G

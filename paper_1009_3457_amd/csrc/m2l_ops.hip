@@ -1,0 +1,134 @@
+// M2L operator generation (Sec. 4.1, Eq. (eq:M2Lmat)): every entry of every
+// offset's scaled operator is computed in FP64 on the device (exact binomial,
+// power by repeated complex multiplication of d^-1) and rounded once to the
+// storage precision.  The paper builds the entries on the fly inside each
+// translation; here the 40 distinct operators of a given p are built once and
+// reused by every level, every launch and the adjoint.
+#include <cmath>
+
+#include "fmm2d_internal.h"
+#include "m2l_bank.h"
+#include "m2l_mixed_bank.h"
+
+namespace fmm2d {
+
+// C(a, b) in FP64: the running product c * (a - b + i) / i stays an exact
+// integer below 2^53 for a <= 40.
+__device__ inline double binom_f64(int a, int b) {
+  double c = 1.0;
+  for (int i = 1; i <= b; ++i) c = c * double(a - b + i) / double(i);
+  return c;
+}
+
+// d^-m for a complex d with |d| >= 2, by m - 1 multiplications of d^-1.
+__device__ inline cd cpow_neg(cd d, int m) {
+  double den = d.re * d.re + d.im * d.im;
+  cd inv = {d.re / den, -d.im / den};
+  cd r = {1.0, 0.0};
+  for (int i = 0; i < m; ++i) r = cmul(r, inv);
+  return r;
+}
+
+// Entry (n, k) of the scaled operator for offset (ox, oy): d = -(ox + i oy).
+__device__ inline cd m2l_entry(int ox, int oy, int n, int k) {
+  cd d = {double(-ox), double(-oy)};
+  cd v = cpow_neg(d, n + k + 1);
+  double c = binom_f64(n + k, k) * ((n & 1) ? -1.0 : 1.0);
+  return {c * v.re, c * v.im};
+}
+
+// Log-potential row entry k for a given d: log d (k = 0), -d^-k / k.
+__device__ inline cd log_row_entry(double dre, double dim, int k) {
+  if (k == 0) return {0.5 * log(dre * dre + dim * dim), atan2(dim, dre)};
+  cd v = cpow_neg(cd{dre, dim}, k);
+  return {-v.re / double(k), -v.im / double(k)};
+}
+
+__device__ inline bool slot_used(int slot, int &ox, int &oy) {
+  ox = slot % 7 - 3;
+  oy = slot / 7 - 3;
+  return (ox < -1 || ox > 1 || oy < -1 || oy > 1);
+}
+
+template <int P>
+__global__ void f32_bank_kernel(float *bank) {
+  using B = F32Bank<P>;
+  const size_t total = B::total_floats;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < total; i += size_t(gridDim.x) * blockDim.x) {
+    float v = 0.0f;
+    if (i < B::a_off + B::a_floats) {
+      size_t e = i - B::a_off;
+      int pos = int(e % B::LS);
+      size_t r = e / B::LS;
+      int lane = int(r % 64);
+      r /= 64;
+      int mt = int(r % B::MT);
+      int slot = int(r / B::MT);
+      int ox, oy;
+      if (pos < 3 * B::S && slot_used(slot, ox, oy)) {
+        int part = pos / B::S, s = pos % B::S;
+        int n = 16 * mt + lane % 16;
+        int k = B::S * (lane / 16) + s;
+        if (n < P) {
+          cd a = m2l_entry(ox, oy, n, k);
+          double x = part == 0 ? a.re : (part == 1 ? a.im : a.re + a.im);
+          v = float(x);
+        }
+      }
+    } else if (i >= B::r_off && i < B::r_off + B::r_floats) {
+      size_t e = i - B::r_off;
+      int ri = int(e % 2);
+      size_t r = e / 2;
+      int s = int(r % B::S);
+      r /= B::S;
+      int kk = int(r % 4);
+      int slot = int(r / 4);
+      int ox, oy;
+      if (slot_used(slot, ox, oy)) {
+        // d = -o, negated as integers: a zero component must be +0 so that the
+        // principal branch of log d is taken (arg d = +pi on the negative axis)
+        cd rv = log_row_entry(double(-ox), double(-oy), B::S * kk + s);
+        v = float(ri ? rv.im : rv.re);
+      }
+    } else if (i >= B::ra_off && i < B::ra_off + B::ra_floats) {
+      size_t e = i - B::ra_off;
+      int ri = int(e % 2);
+      size_t r = e / 2;
+      int row = int(r % 16);
+      r /= 16;
+      int mt = int(r % B::MT);
+      int slot = int(r / B::MT);
+      int n = 16 * mt + row;
+      int ox, oy;
+      if (n < P && slot_used(slot, ox, oy)) {
+        cd rv = log_row_entry(double(ox), double(oy), n);
+        v = float(ri ? rv.im : rv.re);
+      }
+    }
+    bank[i] = v;
+  }
+}
+
+size_t m2l_ops_bytes(int p, int precision) {
+  if (!p_supported(p)) return 0;
+  if (precision == FMM2D_F32) return f32_bank_bytes(p);
+  if (m2l_mixed_supported(p, precision)) return mixed_bank_bytes(p, precision);
+  return 0;
+}
+
+int launch_mixed_ops(int p, int precision, void *ops, hipStream_t s);
+
+int launch_m2l_ops(int p, int precision, void *ops, hipStream_t s) {
+  if (precision != FMM2D_F32) return launch_mixed_ops(p, precision, ops, s);
+  float *bank = static_cast<float *>(ops);
+  dim3 grid(512), block(256);
+  switch (p) {
+    case 8: hipLaunchKernelGGL(f32_bank_kernel<8>, grid, block, 0, s, bank); break;
+    case 12: hipLaunchKernelGGL(f32_bank_kernel<12>, grid, block, 0, s, bank); break;
+    case 16: hipLaunchKernelGGL(f32_bank_kernel<16>, grid, block, 0, s, bank); break;
+    case 20: hipLaunchKernelGGL(f32_bank_kernel<20>, grid, block, 0, s, bank); break;
+  }
+  return check_launch("m2l operator bank");
+}
+
+}  // namespace fmm2d

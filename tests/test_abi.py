@@ -1,0 +1,117 @@
+"""Host-side checks of libfmm2d.so (no GPU needed): every symbol declared in
+include/fmm2d.h is exported, the host-only queries are right, and invalid
+arguments are rejected on the host before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1009_3457_amd import _binding
+    return _binding.load()
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fmm2d.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fmm2d_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = _lib()
+    names = _declared()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_1009_3457_amd import _binding
+    assert sorted(_binding._SIGNATURES) == names
+
+
+def test_abi_version_and_queries():
+    lib = _lib()
+    assert lib.fmm2d_abi_version() == 1
+    for d in range(0, 13):
+        assert lib.fmm2d_num_boxes(d) == (4 ** (d + 1) - 1) // 3
+    assert lib.fmm2d_num_boxes(13) == -1
+    for l in range(0, 14):
+        assert lib.fmm2d_level_offset(l) == (4 ** l - 1) // 3
+
+
+def test_translation_count_matches_oracle_brute_force():
+    lib = _lib()
+    for l in range(2, 6):
+        ns = 1 << l
+        brute = sum(oracle.interaction_list(l, ix, iy).size for ix in range(ns) for iy in range(ns))
+        assert lib.fmm2d_translation_count(l, l) == brute
+    assert lib.fmm2d_translation_count(2, 8) == 2316900
+    assert lib.fmm2d_translation_count(2, 9) == 9351840
+    assert lib.fmm2d_translation_count(2, 10) == 37577436
+    assert lib.fmm2d_translation_count(1, 4) == -1
+
+
+def test_operator_bank_sizes():
+    lib = _lib()
+    for p in (8, 12, 16, 20):
+        assert lib.fmm2d_m2l_operators_bytes(p, 0) > 0
+    assert lib.fmm2d_m2l_operators_bytes(10, 0) == 0
+    assert lib.fmm2d_m2l_operators_bytes(12, 7) == 0
+
+
+def test_build_tree_workspace_is_host_only():
+    lib = _lib()
+    assert lib.fmm2d_build_tree_workspace(1 << 20, 8) > 4 * 4 * (1 << 20)
+    assert lib.fmm2d_build_tree_workspace(-1, 8) == 0
+    assert lib.fmm2d_build_tree_workspace(10, 13) == 0
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("args,code", [
+    # (depth, p, lmin, lmax, precision, ops_bytes) -> status
+    ((8, 11, 2, 8, 0, 1 << 30), -2),
+    ((13, 12, 2, 8, 0, 1 << 30), -3),
+    ((1, 12, 2, 8, 0, 1 << 30), -3),
+    ((8, 12, 1, 8, 0, 1 << 30), -7),
+    ((8, 12, 2, 9, 0, 1 << 30), -7),
+    ((8, 12, 5, 4, 0, 1 << 30), -7),
+    ((8, 12, 2, 8, 0, 16), -5),
+    ((8, 12, 2, 8, 9, 1 << 30), -1),
+])
+def test_m2l_rejects_bad_arguments_on_host(args, code):
+    lib = _lib()
+    depth, p, lmin, lmax, prec, nbytes = args
+    rc = lib.fmm2d_m2l(FAKE, ctypes.c_void_p(0x2000), None, depth, p, lmin, lmax, prec, FAKE, nbytes, None)
+    assert rc == code
+    assert lib.fmm2d_last_error().decode()
+    rc = lib.fmm2d_m2l_backward(FAKE, None, ctypes.c_void_p(0x2000), depth, p, lmin, lmax, prec, FAKE,
+                                nbytes, None)
+    assert rc == code
+
+
+def test_null_pointers_rejected_on_host():
+    lib = _lib()
+    assert lib.fmm2d_m2l(None, FAKE, None, 8, 12, 2, 8, 0, FAKE, 1 << 30, None) == -1
+    assert lib.fmm2d_m2l(FAKE, FAKE, None, 8, 12, 2, 8, 0, FAKE, 1 << 30, None) == -1  # in == out
+    assert lib.fmm2d_p2m(None, FAKE, FAKE, 8, 12, FAKE, None) == -1
+    assert lib.fmm2d_l2l(FAKE, None, FAKE, FAKE, 8, 12, None) == -1
+    assert lib.fmm2d_build_tree(FAKE, 10, 8, FAKE, FAKE, FAKE, 0, None) == -5
+    assert lib.fmm2d_build_tree(FAKE, -1, 8, FAKE, FAKE, FAKE, 1 << 30, None) == -1
+    assert lib.fmm2d_gather(FAKE, FAKE, 10, 0, ctypes.c_void_p(0x3000), None) == -1
+    assert lib.fmm2d_m2l_operators(12, 0, None, 1 << 30, None) == -1
+    assert lib.fmm2d_p2p(FAKE, FAKE, FAKE, FAKE, FAKE, -5, 8, FAKE, FAKE, None) == -1
+
+
+def test_mixed_precision_reported_unsupported_when_not_built():
+    lib = _lib()
+    for prec in (1, 2):
+        for p in (8, 12, 16, 20):
+            if lib.fmm2d_m2l_operators_bytes(p, prec) == 0:
+                rc = lib.fmm2d_m2l(FAKE, ctypes.c_void_p(0x2000), None, 8, p, 2, 8, prec, FAKE, 1 << 30, None)
+                assert rc == -2

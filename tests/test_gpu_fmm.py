@@ -1,0 +1,176 @@
+"""GPU parity of the whole FMM (every stage in the library's kernels) and of
+its gradient against the FP64 oracle with the same tree and p, plus the
+boundary stages one by one."""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as sy
+from tests._inputs import level_slices, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1009_3457_amd as P
+    return P
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+# ------------------------------------------------------------ stages ---
+
+@pytest.mark.parametrize("n,depth,kind", [(0, 3, "uniform"), (1, 2, "uniform"), (1000, 4, "uniform"),
+                                          (50000, 6, "mixed"), (1 << 20, 8, "uniform")])
+def test_build_tree_bit_exact(P, n, depth, kind):
+    print(f"build_tree n={n} depth={depth}", flush=True)
+    xy = sy.uniform(n, 4) if kind == "uniform" else sy.mixed(n, 4)
+    if n >= 4:  # points on the upper boundary are clamped into the last leaf
+        xy[0] = (1.0, 1.0)
+        xy[1] = (0.0, 1.0)
+        xy[2] = xy[3]  # a duplicate point: equal keys keep input order
+    perm, ls = P.build_tree(_t(xy), depth)
+    perm_r, ls_r = oracle.build_tree(xy.astype(np.float64), depth)
+    assert np.array_equal(perm.cpu().numpy(), perm_r)
+    assert np.array_equal(ls.cpu().numpy(), ls_r)
+
+
+def test_build_tree_rejects_points_outside(P):
+    xy = sy.uniform(100, 1)
+    xy[17] = (0.5, 1.25)
+    with pytest.raises(P.FMMError):
+        P.build_tree(_t(xy), 4)
+    xy[17] = (np.nan, 0.5)
+    with pytest.raises(P.FMMError):
+        P.build_tree(_t(xy), 4)
+
+
+@pytest.mark.parametrize("p", [8, 12, 20])
+def test_p2m_m2m_match_oracle(P, p):
+    depth, n = 6, 40000
+    xy = sy.mixed(n, 8)
+    q = sy.charges(n, 9)
+    perm, ls = P.build_tree(_t(xy), depth)
+    xs, qs = P.gather(_t(xy), perm), P.gather(_t(q), perm)
+    M = P.m2m(P.p2m(xs, qs, ls, depth, p), depth, p).cpu().numpy()
+    pr, lr = oracle.build_tree(xy.astype(np.float64), depth)
+    Mr = oracle.m2m(oracle.p2m(xy[pr].astype(np.float64), q[pr].astype(np.float64), lr, depth, p), depth, p)
+    Mr = oracle.scale_multipoles(Mr, depth)
+    for l, sl in level_slices(depth, lmin=0):
+        assert rel(M[sl], Mr[sl]) < 1e-5, (l, rel(M[sl], Mr[sl]))
+
+
+@pytest.mark.parametrize("p", [8, 12, 20])
+def test_l2l_l2p_match_oracle(P, p):
+    depth = 5
+    g = np.random.Generator(np.random.PCG64(p))
+    nb = oracle.num_boxes(depth)
+    Lm = ((g.standard_normal((nb, p)) + 1j * g.standard_normal((nb, p))) * 0.5 ** np.arange(p)).astype(np.complex64)
+    bm = (g.standard_normal(nb) + 1j * g.standard_normal(nb)).astype(np.complex64)
+    Lm[:oracle.level_offset(2)] = 0
+    bm[:oracle.level_offset(2)] = 0
+    L, b = P.l2l(_t(Lm), _t(bm), depth, p)
+    Lr, br = oracle.l2l(oracle.unscale_locals(Lm.astype(np.complex128), depth), bm.astype(np.complex128), depth, p)
+    Lg = L.cpu().numpy()
+    for l, sl in level_slices(depth):
+        assert rel(Lg[sl], oracle.scale_locals(Lr, depth)[sl]) < 1e-12
+        assert rel(b.cpu().numpy()[sl], br[sl]) < 1e-12
+    t = sy.uniform(3000, 5)
+    tp, tls = P.build_tree(_t(t), depth)
+    ts = P.gather(_t(t), tp)
+    phi, f = P.l2p(ts, tls, L, b, depth, p)
+    tpr, tlsr = oracle.build_tree(t.astype(np.float64), depth)
+    phir, fr = oracle.l2p(t[tpr].astype(np.float64), tlsr, Lr, br, depth, p)
+    assert rel(phi.cpu().numpy(), phir) < 2e-7
+    assert rel(f.cpu().numpy(), fr) < 2e-7
+
+
+def test_p2p_matches_oracle(P):
+    depth, n = 5, 20000
+    xy = sy.mixed(n, 12)
+    q = sy.charges(n, 13)
+    t = np.concatenate([sy.uniform(3000, 14), xy[:500]])  # includes coincident pairs
+    perm, ls = P.build_tree(_t(xy), depth)
+    tp, tls = P.build_tree(_t(t), depth)
+    xs, qs, ts = P.gather(_t(xy), perm), P.gather(_t(q), perm), P.gather(_t(t), tp)
+    phi, f = P.p2p(xs, qs, ls, ts, tls, depth)
+    pr, lr = oracle.build_tree(xy.astype(np.float64), depth)
+    tpr, tlr = oracle.build_tree(t.astype(np.float64), depth)
+    phir, fr = oracle.p2p(xy[pr].astype(np.float64), q[pr].astype(np.float64), lr,
+                          t[tpr].astype(np.float64), tlr, depth)
+    assert rel(phi.cpu().numpy().real, phir.real) < 1e-5
+    assert rel(f.cpu().numpy(), fr) < 1e-5
+
+
+# ---------------------------------------------------------- pipeline ---
+
+@pytest.mark.parametrize("n,depth,p,kind", [(4096, 4, 8, "uniform"), (4096, 4, 12, "uniform"),
+                                            (60000, 6, 16, "mixed"), (30000, 5, 20, "mixed")])
+def test_fmm_potential_matches_oracle(P, n, depth, p, kind):
+    print(f"fmm n={n} depth={depth} p={p}", flush=True)
+    xy = sy.uniform(n, 21) if kind == "uniform" else sy.mixed(n, 21)
+    q = sy.charges(n, 22)
+    t = sy.uniform(2048, 23)
+    phi, f = P.potential(_t(xy), _t(q), _t(t), depth=depth, p=p)
+    phir, fr = oracle.fmm(xy.astype(np.float64), q.astype(np.float64), t.astype(np.float64), depth, p)
+    assert rel(phi.cpu().numpy().real, phir.real) < 1e-5
+    assert rel(f.cpu().numpy(), fr) < 1e-5
+
+
+def test_fmm_c1_against_direct_sum(P):
+    """C1: N = 4096 uniform, depth 4, p = 8 at the sources themselves."""
+    xy = sy.uniform(4096, 1)
+    q = sy.charges(4096, 2)
+    phi, f = P.potential(_t(xy), _t(q), None, depth=4, p=8)
+    phid, fd = oracle.direct(xy.astype(np.float64), q.astype(np.float64), xy.astype(np.float64))
+    assert rel(phi.cpu().numpy().real, phid.real) < 2e-5
+    assert rel(f.cpu().numpy(), fd) < 1e-4
+
+
+@pytest.mark.parametrize("n,depth,p", [(4096, 4, 12), (1 << 20, 8, 12)])
+def test_gradient_matches_oracle(P, n, depth, p):
+    """Loss sum over 4096 targets of (Re phi)^2: grad w.r.t. charges and
+    positions against the FP64 oracle's transpose chain (same tree, same p)."""
+    import torch
+    print(f"gradient n={n} depth={depth} p={p}", flush=True)
+    xy = sy.uniform(n, 31)
+    q = sy.charges(n, 32)
+    t = sy.uniform(4096, 33)
+    xg = _t(xy).requires_grad_(True)
+    qg = _t(q).requires_grad_(True)
+    phi, _ = P.potential(xg, qg, _t(t), depth=depth, p=p)
+    loss = (phi.real ** 2).sum()
+    loss.backward()
+    phir, _ = oracle.fmm(xy.astype(np.float64), q.astype(np.float64), t.astype(np.float64), depth, p)
+    gq_r, gxy_r = oracle.fmm_grad(xy.astype(np.float64), q.astype(np.float64), t.astype(np.float64), depth, p,
+                                  (2 * phir.real).astype(np.complex128))
+    assert rel(qg.grad.cpu().numpy(), gq_r) < 1e-5
+    assert rel(xg.grad.cpu().numpy(), gxy_r) < 1e-5
+    del torch
+
+
+def test_m2l_autograd_matches_adjoint(P):
+    """torch.autograd through the M2L Function: grad of Re<w, L> equals the
+    conjugated adjoint, checked against the oracle transpose."""
+    import torch
+    depth, p = 4, 12
+    g = np.random.Generator(np.random.PCG64(3))
+    nb = oracle.num_boxes(depth)
+    M = ((g.standard_normal((nb, p)) + 1j * g.standard_normal((nb, p))) * 0.5 ** np.arange(p)).astype(np.complex64)
+    W = (g.standard_normal((nb, p)) + 1j * g.standard_normal((nb, p))).astype(np.complex64)
+    Mt = _t(M).requires_grad_(True)
+    L, b = P.m2l(Mt, depth, p)
+    loss = (L * _t(W)).real.sum()
+    loss.backward()
+    # l = Re sum W L = Re sum W A M  =>  grad_M = conj(A^T W) (PyTorch convention)
+    W_un = oracle.scale_locals(W.astype(np.complex128), depth)
+    ref = np.conj(oracle.unscale_multipoles(oracle.m2l_transpose(W_un, None, depth, p), depth))
+    assert rel(Mt.grad.cpu().numpy(), ref) < 1e-5
+    del torch
