@@ -4,23 +4,34 @@
 // For every target box t of levels lmin..lmax (scaled basis, see fmm2d.h):
 //   L~(t) = sum_{o in O_c(t)} A~_o M~(t + o),
 //   b(t)  = sum_o [ r_o . M~(t + o) + log(h) M~_0(t + o) ].
-// A workgroup of four waves owns an 8x8 target tile (m2l_common.h); wave w
-// handles the 16 boxes of child class w.  For each of the class's 27 offsets
-// the wave multiplies the offset's operator (rows = output orders n, 16 per
-// M tile) by the 16 source expansions M~(t + o) (columns = boxes) with
-// v_mfma_f32_16x16x4_f32, using Gauss's three real products per complex
-// product (m2l_bank.h).  The source expansions of the whole tile are staged in
-// LDS once and read by all 27 offsets of all four classes.  The reduction over
-// the interaction list happens in the MFMA accumulators in a fixed offset
-// order, so each L~(t) is written exactly once and results are reproducible.
-// The log row b is a one-row product done on the vector ALU from the same
-// staged operands, reduced across the four k-groups of a wave with lane
-// shuffles.
+//
+// Work decomposition (m2l_common.h): 8x8 target tiles.  The 16 boxes of one
+// child class of a tile share one list of 27 offsets; for each offset they
+// form the 16 columns of one product with a single operator (MFMA rows =
+// output orders n, 16 per M tile), run on v_mfma_f32_16x16x4_f32 in Gauss's
+// three-real-product form of the complex product (m2l_bank.h).  Two waves
+// own one class: wave (c, h) takes offsets 14h .. 14h + 13 of the class
+// list.  The reduction over the interaction list happens in the MFMA
+// accumulators in a fixed offset order; the second half's partial sums are
+// added to the first half's through LDS, always in that order, and each
+// L~(t) is written once, so results are bit-reproducible.
+//
+// The kernel is persistent: one workgroup of eight waves (two per SIMD) per
+// compute unit walks the tiles g, g + G, g + 2G, ...  A wave's class and
+// offsets never change, so for p <= 16 its 14 operator fragments are loaded
+// into registers once and reused for every tile; only source expansions
+// move.  The 12x12 source block of the next tile is fetched from HBM into
+// registers while the current tile is computed, then written to the second
+// of two LDS buffers.  For p = 20 (two M tiles) the fragments do not fit and
+// are streamed from the L2-resident bank one offset ahead.
+//
+// The log row b rides in spare MFMA rows when p is not a multiple of 16
+// (m2l_bank.h); for p = 16 it is computed by m2l_logrow.hip.
 //
 // The adjoint uses the same stencil: since s in IL(t) <=> t in IL(s) and
-// A~(d)^T = -A~(-d), the transpose gathers over s's own list with the
-// negated forward operator of each offset; the log-row part becomes a rank-one
-// update per offset with the row at d = +o.
+// A~(d)^T = -A~(-d), the transpose gathers over s's own list with the negated
+// forward operator of each offset.  Its log-row part, a contraction of gb
+// over the offset list, runs as seven more MFMA k-steps (m2l_bank.h).
 #include "fmm2d_internal.h"
 #include "m2l_bank.h"
 #include "m2l_common.h"
@@ -28,212 +39,447 @@
 namespace fmm2d {
 
 typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
 
-template <int P, bool ADJ>
-struct F32Acc {
-  static constexpr int MT = F32Bank<P>::MT;
-  f4_t t[MT][3];       // Gauss products T1, T2, T3 per M tile
-  float br, bi;        // forward: partial log-row sum over this lane's k values
-  float s0r, s0i;      // forward: sum of M~_0 over the list (k-group 0 only)
-  float gr[MT][4];     // adjoint: rank-one log-row part, per output row
-  float gi[MT][4];
-  float gsr, gsi;      // adjoint: sum of gb over the list
+constexpr int kThreads = 512;  // 8 waves: class w & 3, offset half w >> 2
+constexpr int kHalf = 14;      // offsets per wave (14 and 13)
+constexpr int kGbHalf = 4;     // adjoint log-row k-steps of the first half (4 and 3)
+
+template <int P>
+struct F32Cfg {
+  using B = F32Bank<P>;
+  static constexpr int S = B::S, MT = B::MT, LS = B::LS;
+  static constexpr int NA = 2 * S;                          // floats of an A or B fragment (Re, Im)
+  static constexpr bool kRegBank = (MT == 1);               // operators held in registers
+  static constexpr bool kLogInRows = B::kLogInRows;
+  static constexpr int kChunks = kRegBoxes * P / 2;         // float4 chunks of a source block
+  static constexpr int kPf = (kChunks + kThreads - 1) / kThreads;  // chunks per thread
+  static constexpr int kLdsX = 4 * kRegBoxes * LS;          // floats of one source buffer
 };
 
-// One class (CX, CY): all 27 offsets unrolled at compile time.
-template <int P, bool ADJ, int CX, int CY>
-__device__ __forceinline__ void m2l_f32_class(const float *__restrict__ lx, const float2 *__restrict__ lgb,
-                                              const float *__restrict__ bank, int lane, F32Acc<P, ADJ> &a) {
+// Source block of one tile held in registers between the global load and the
+// LDS store.  Every load is issued unconditionally (from box 0 when the box
+// lies outside the grid) and masked when stored, so no branch forces an
+// early wait.
+template <int P>
+struct Prefetch {
+  float4 v[F32Cfg<P>::kPf];
+  float2 g;
+  uint32_t ok;  // bit r: chunk r is inside the grid; bit 31: the gb entry is
+};
+
+struct TileGeo {
+  int level, nside, X0, Y0;
+  int64_t off;
+};
+
+__device__ inline TileGeo tile_geo(const TileMap &map, int t) {
+  TileGeo g;
+  int tile;
+  tile_of(map, t, g.level, tile);
+  g.nside = 1 << g.level;
+  uint32_t tX, tY;
+  unmorton2(uint32_t(tile), tX, tY);
+  g.X0 = int(tX) * kTile;
+  g.Y0 = int(tY) * kTile;
+  g.off = level_off(g.level);
+  return g;
+}
+
+template <int P, bool ADJ>
+__device__ inline void prefetch_issue(Prefetch<P> &pf, const TileGeo &g, const float2 *__restrict__ X,
+                                      const float2 *__restrict__ gbin, int tid) {
+  using C = F32Cfg<P>;
+  pf.ok = 0;
+#pragma unroll
+  for (int r = 0; r < C::kPf; ++r) {
+    const int e = tid + kThreads * r;
+    const int rb = e / (P / 2), q = e - rb * (P / 2);
+    const int gx = g.X0 - kHalo + rb % kReg, gy = g.Y0 - kHalo + rb / kReg;
+    const bool in = e < C::kChunks && gx >= 0 && gy >= 0 && gx < g.nside && gy < g.nside;
+    const int64_t idx = in ? (g.off + morton2(uint32_t(gx), uint32_t(gy))) * P + 2 * q : 0;
+    pf.v[r] = *reinterpret_cast<const float4 *>(X + idx);
+    pf.ok |= uint32_t(in) << r;
+  }
+  if (ADJ && gbin) {  // gbin is uniform
+    const int gx = g.X0 - kHalo + tid % kReg, gy = g.Y0 - kHalo + tid / kReg;
+    const bool in = tid < kRegBoxes && gx >= 0 && gy >= 0 && gx < g.nside && gy < g.nside;
+    pf.g = gbin[in ? g.off + morton2(uint32_t(gx), uint32_t(gy)) : 0];
+    pf.ok |= uint32_t(in) << 31;
+  }
+}
+
+// x[kk][box][q S + s] holds part q (0: Re, 1: Im) of coefficient k = S kk + s;
+// gb[box] the adjoint's log-row input (entry kRegBoxes stays zero).
+template <int P, bool ADJ>
+__device__ inline void prefetch_store(const Prefetch<P> &pf, float *__restrict__ lx, float2 *__restrict__ lgb,
+                                      int tid) {
+  using C = F32Cfg<P>;
+  constexpr int S = C::S, LS = C::LS;
+#pragma unroll
+  for (int r = 0; r < C::kPf; ++r) {
+    const int e = tid + kThreads * r;
+    if (e < C::kChunks) {
+      const int rb = e / (P / 2), q = e - rb * (P / 2);
+      const bool in = (pf.ok >> r) & 1u;
+      const float re[2] = {in ? pf.v[r].x : 0.f, in ? pf.v[r].z : 0.f};
+      const float im[2] = {in ? pf.v[r].y : 0.f, in ? pf.v[r].w : 0.f};
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = 2 * q + h;
+        const int kk = k / S, s = k - kk * S;
+        float *d = lx + (kk * kRegBoxes + rb) * LS;
+        d[s] = re[h];
+        d[S + s] = im[h];
+      }
+    }
+  }
+  if (ADJ && tid <= kRegBoxes)
+    lgb[tid] = (tid < kRegBoxes && (pf.ok >> 31)) ? pf.g : make_float2(0.f, 0.f);
+}
+
+template <int P, bool ADJ>
+struct LdsF32 {
+  using C = F32Cfg<P>;
+  static constexpr int MT = C::MT;
+  // partial sums of the second offset half: accumulators (+ sum of gb for p = 16)
+  static constexpr bool kGbSumLanes = ADJ && !F32Bank<P>::kGbSumRow;
+  static constexpr int kN = MT * 12 + (kGbSumLanes ? 2 : 0);
+  float x[2][C::kLdsX];
+  float2 gb[2][ADJ ? kRegBoxes + 1 : 1];
+  float red[4][kN][64];
+};
+
+template <int P, bool ADJ, int CX, int CY, int HALF>
+__device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__restrict__ X,
+                                            const float2 *__restrict__ gbin, float2 *__restrict__ Y,
+                                            float2 *__restrict__ bout, const float *__restrict__ bank,
+                                            const TileMap &map, int ntiles, int tid) {
+  using C = F32Cfg<P>;
   using B = F32Bank<P>;
-  constexpr int S = B::S, MT = B::MT, LS = B::LS;
+  constexpr int S = C::S, MT = C::MT, LS = C::LS, NA = C::NA;
+  constexpr int I0 = HALF * kHalf, NI = HALF ? 27 - kHalf : kHalf;
+  constexpr int G0 = HALF * kGbHalf, NG = HALF ? B::kGbSteps - kGbHalf : kGbHalf;
+  constexpr int kN = LdsF32<P, ADJ>::kN;
+  constexpr bool kGbSumLanes = LdsF32<P, ADJ>::kGbSumLanes;
+
+  constexpr int cls = CX + 2 * CY;
+  constexpr int sx = 1 - 2 * CX, sy = 1 - 2 * CY;  // mirror of class (0, 0)'s offsets
+  const int lane = tid & 63;
   const int j = lane & 15, kk = lane >> 4;
   const int tx = 2 * (j & 3) + CX, ty = 2 * (j >> 2) + CY;
-  const float *lbase = lx + (kk * kRegBoxes + (ty + kHalo) * kReg + (tx + kHalo)) * LS;
-  const float *abase = bank + B::a_off + size_t(lane) * LS;
+
+  // The bank is read through a buffer descriptor: one per-lane VGPR offset
+  // plus a scalar offset per fragment, so no per-offset vector addresses stay
+  // live; reads past the bank's end would return zero.
+  const __amdgpu_buffer_rsrc_t rsrc =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(bank), 0, int(B::total_floats * 4), 0x00020000);
+  const int alane = lane * LS * 4;
+  auto bank_frag = [&](int slot, int mt, int e) {
+    const int soff = int((B::a_off + (size_t(slot) * MT + mt) * 64 * LS) * 4) + 16 * e;
+    // explicitly typed result, cast whole: subscripting the builtin's
+    // deduced result type compiles to a single-dword load here
+    const u32x4_t u = __builtin_amdgcn_raw_buffer_load_b128(rsrc, alane, soff, 0);
+    return __builtin_bit_cast(float4, u);
+  };
+
+  // operator fragments of this wave's offsets, held for the whole kernel (p <= 16)
+  float areg[C::kRegBank ? NI : 1][NA];
+  if (C::kRegBank) {
 #pragma unroll
-  for (int oyi = 0; oyi < 6; ++oyi) {
-#pragma unroll
-    for (int oxi = 0; oxi < 6; ++oxi) {
-      const int ox = oxi - 2 - CX, oy = oyi - 2 - CY;
-      if (ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1) continue;  // resolved at compile time
-      const int slot = slot_of(ox, oy);
-      // B operand: this lane's k values of the source box t + o
-      float bx[LS];
-      const float4 *bs = reinterpret_cast<const float4 *>(lbase + (oy * kReg + ox) * LS);
+    for (int i = 0; i < NI; ++i) {
+      const int slot = slot_of(sx * kOff00.ox[I0 + i], sy * kOff00.oy[I0 + i]);
 #pragma unroll
       for (int e = 0; e < LS / 4; ++e) {
-        float4 v = bs[e];
-        bx[4 * e] = v.x;
-        bx[4 * e + 1] = v.y;
-        bx[4 * e + 2] = v.z;
-        bx[4 * e + 3] = v.w;
+        const float4 v = bank_frag(slot, 0, e);
+        if (4 * e < NA) areg[i][4 * e] = v.x;
+        if (4 * e + 1 < NA) areg[i][4 * e + 1] = v.y;
+        if (4 * e + 2 < NA) areg[i][4 * e + 2] = v.z;
+        if (4 * e + 3 < NA) areg[i][4 * e + 3] = v.w;
+      }
+    }
+  }
+  // adjoint log-row fragments (A) and this lane's gb source entries (B)
+  float2 ga[ADJ ? NG : 1][MT];
+  int gbo[ADJ ? NG : 1];
+  if (ADJ) {
+    const int glane = lane * 8;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int soff = int((B::ga_off + ((size_t(cls) * B::kGbSteps + G0 + g) * MT + mt) * 64 * 2) * 4);
+        const u32x2_t u = __builtin_amdgcn_raw_buffer_load_b64(rsrc, glane, soff, 0);
+        ga[g][mt] = __builtin_bit_cast(float2, u);
+      }
+      const int kap = 4 * (G0 + g) + kk;  // entry of the class's offset list
+      int o = kRegBoxes;                  // the zero entry
+#pragma unroll
+      for (int q = 0; q < 27; ++q)
+        if (q == kap) o = (ty + kHalo + sy * kOff00.oy[q]) * kReg + (tx + kHalo + sx * kOff00.ox[q]);
+      gbo[g] = o;
+    }
+  }
+
+  const int lbase = (kk * kRegBoxes + (ty + kHalo) * kReg + (tx + kHalo)) * LS;
+  constexpr int dX = sx * LS, dY = sy * kReg * LS;
+  const float ln2 = 0.69314718055994530942f;
+
+  int t = blockIdx.x;
+  TileGeo geo = tile_geo(map, t);
+  int cur = 0;
+  for (;;) {
+    // LDS contents change every tile: keep the compiler from caching LDS
+    // reads in registers across tiles
+    asm volatile("" ::: "memory");
+    // Opaque per tile: stops the per-use sums Ar + Ai from being hoisted out
+    // of the tile loop into extra registers (emits no instructions).
+    if (C::kRegBank) {
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int e = 0; e < NA; ++e) asm volatile("" : "+v"(areg[i][e]));
+    }
+    const int tn = t + int(gridDim.x);
+    const bool has_next = tn < ntiles;
+    TileGeo ngeo = geo;
+    Prefetch<P> pf;
+    if (has_next) {
+      ngeo = tile_geo(map, tn);
+      prefetch_issue<P, ADJ>(pf, ngeo, X, gbin, tid);
+    }
+
+    const float *L = sm.x[cur];
+    f4_t acc[MT][3];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) acc[mt][q] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+    float bcur[LS], bnxt[LS];
+    constexpr int AM = C::kRegBank ? 1 : MT, AL = C::kRegBank ? 1 : LS;
+    float acur[AM][AL], anxt[AM][AL];
+    auto load_b = [&](float (&dst)[LS], int i) {
+      const float4 *bs =
+          reinterpret_cast<const float4 *>(L + lbase + kOff00.ox[I0 + i] * dX + kOff00.oy[I0 + i] * dY);
+#pragma unroll
+      for (int e = 0; e < LS / 4; ++e) {
+        const float4 v = bs[e];
+        dst[4 * e] = v.x;
+        dst[4 * e + 1] = v.y;
+        dst[4 * e + 2] = v.z;
+        dst[4 * e + 3] = v.w;
+      }
+    };
+    auto load_a = [&](float (&dst)[AM][AL], int i) {
+      if (!C::kRegBank) {
+        const int slot = slot_of(sx * kOff00.ox[I0 + i], sy * kOff00.oy[I0 + i]);
+#pragma unroll
+        for (int mt = 0; mt < AM; ++mt)
+#pragma unroll
+          for (int e = 0; e < AL / 4; ++e) {
+            const float4 v = bank_frag(slot, mt, e);
+            dst[mt][4 * e] = v.x;
+            dst[mt][4 * e + 1] = v.y;
+            dst[mt][4 * e + 2] = v.z;
+            dst[mt][4 * e + 3] = v.w;
+          }
+      }
+    };
+
+    load_b(bcur, 0);
+    load_a(acur, 0);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      if (i + 1 < NI) {
+        load_b(bnxt, i + 1);
+        load_a(anxt, i + 1);
       }
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        float ax[LS];
-        const float4 *as = reinterpret_cast<const float4 *>(abase + size_t(slot * MT + mt) * 64 * LS);
-#pragma unroll
-        for (int e = 0; e < LS / 4; ++e) {
-          float4 v = as[e];
-          ax[4 * e] = v.x;
-          ax[4 * e + 1] = v.y;
-          ax[4 * e + 2] = v.z;
-          ax[4 * e + 3] = v.w;
-        }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-          a.t[mt][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax[s], bx[s], a.t[mt][0], 0, 0, 0);
-          a.t[mt][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax[S + s], bx[S + s], a.t[mt][1], 0, 0, 0);
-          a.t[mt][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax[2 * S + s], bx[2 * S + s], a.t[mt][2], 0, 0, 0);
+          const float a0 = C::kRegBank ? areg[i][s] : acur[mt % AM][s % AL];
+          const float a1 = C::kRegBank ? areg[i][S + s] : acur[mt % AM][(S + s) % AL];
+          const float a2 = a0 + a1, b2 = bcur[s] + bcur[S + s];  // third Gauss operands
+          acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bcur[s], acc[mt][0], 0, 0, 0);
+          acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bcur[S + s], acc[mt][1], 0, 0, 0);
+          acc[mt][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b2, acc[mt][2], 0, 0, 0);
         }
       }
-      if (!ADJ) {
-        const float2 *r = reinterpret_cast<const float2 *>(bank + B::r_off) + (slot * 4 + kk) * S;
+      // keep the software pipeline as written: operands of offset i+1 are
+      // loaded during offset i, not hoisted further (register pressure)
+      __builtin_amdgcn_sched_barrier(0);
+      if (i + 1 < NI) {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-          float2 rv = r[s];
-          a.br += rv.x * bx[s] - rv.y * bx[S + s];
-          a.bi += rv.x * bx[S + s] + rv.y * bx[s];
+        for (int e = 0; e < LS; ++e) bcur[e] = bnxt[e];
+#pragma unroll
+        for (int mt = 0; mt < AM; ++mt)
+#pragma unroll
+          for (int e = 0; e < AL; ++e) acur[mt][e] = anxt[mt][e];
+      }
+    }
+
+    // adjoint log-row part: k-steps over the offset list (B operand = gb)
+    float gsr = 0.f, gsi = 0.f;
+    if (ADJ) {
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const float2 gv = sm.gb[cur][gbo[g]];
+        if (kGbSumLanes) {
+          gsr += gv.x;
+          gsi += gv.y;
         }
-        a.s0r += bx[0];
-        a.s0i += bx[S];
-      } else {
-        const int rb = (ty + oy + kHalo) * kReg + (tx + ox + kHalo);
-        const float2 g = lgb[rb];
-        a.gsr += g.x;
-        a.gsi += g.y;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          const float4 *r = reinterpret_cast<const float4 *>(bank + B::ra_off) + ((slot * MT + mt) * 16 + kk * 4) / 2;
-          float4 r01 = r[0], r23 = r[1];
-          float rr[4] = {r01.x, r01.z, r23.x, r23.z}, ri[4] = {r01.y, r01.w, r23.y, r23.w};
+          const float2 a = ga[g][mt];
+          acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, gv.x, acc[mt][0], 0, 0, 0);
+          acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, gv.y, acc[mt][1], 0, 0, 0);
+          acc[mt][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, gv.x + gv.y, acc[mt][2], 0, 0, 0);
+        }
+      }
+    }
+
+    // ---- combine the two offset halves (fixed order: first + second)
+    float part[kN];
+    {
+      int n = 0;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            a.gr[mt][i] += rr[i] * g.x - ri[i] * g.y;
-            a.gi[mt][i] += rr[i] * g.y + ri[i] * g.x;
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) part[n++] = acc[mt][q][e];
+      if (kGbSumLanes) {
+        part[n++] = gsr;
+        part[n++] = gsi;
+      }
+    }
+    if (HALF == 1) {
+#pragma unroll
+      for (int n = 0; n < kN; ++n) sm.red[cls][n][lane] = part[n];
+    }
+    __syncthreads();
+    if (HALF == 0) {
+#pragma unroll
+      for (int n = 0; n < kN; ++n) part[n] += sm.red[cls][n][lane];
+      const int gx = geo.X0 + tx, gy = geo.Y0 + ty;
+      const bool valid = gx < geo.nside && gy < geo.nside;
+      const int64_t gbox = geo.off + morton2(uint32_t(gx), uint32_t(gy));
+      const float logh = -float(geo.level) * ln2;
+      float sgr = 0.f, sgi = 0.f;  // adjoint: sum of gb over the list, for n = 0
+      if (ADJ) {
+        if (kGbSumLanes) {  // each k-group holds part of the sum
+          sgr = part[MT * 12];
+          sgi = part[MT * 12 + 1];
+          sgr += __shfl_xor(sgr, 16);
+          sgi += __shfl_xor(sgi, 16);
+          sgr += __shfl_xor(sgr, 32);
+          sgi += __shfl_xor(sgi, 32);
+        } else {  // row p + 2 holds -sum gb: fetch it from the lane that owns it
+          constexpr int row = P + 2, mtr = row / 16, kkr = (row % 16) / 4, er = row % 4;
+          const float t1 = part[mtr * 12 + er], t2 = part[mtr * 12 + 4 + er], t3 = part[mtr * 12 + 8 + er];
+          sgr = -__shfl(t1 - t2, j + 16 * kkr);
+          sgi = -__shfl(t3 - t1 - t2, j + 16 * kkr);
+        }
+      }
+      if (valid) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int n0 = 16 * mt + 4 * kk;
+          float yr[4], yi[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float t1 = part[mt * 12 + q], t2 = part[mt * 12 + 4 + q], t3 = part[mt * 12 + 8 + q];
+            yr[q] = t1 - t2;
+            yi[q] = t3 - t1 - t2;
+            if (ADJ) {
+              yr[q] = -yr[q];
+              yi[q] = -yi[q];
+            }
+          }
+          if (n0 < P) {
+            if (ADJ && n0 == 0) {
+              yr[0] += logh * sgr;
+              yi[0] += logh * sgi;
+            }
+            float4 *dst = reinterpret_cast<float4 *>(Y + gbox * P + n0);
+            dst[0] = make_float4(yr[0], yi[0], yr[1], yi[1]);
+            dst[1] = make_float4(yr[2], yi[2], yr[3], yi[3]);
+          } else if (!ADJ && C::kLogInRows && n0 == P && bout) {
+            bout[gbox] = make_float2(yr[0] + logh * yr[1], yi[0] + logh * yi[1]);
           }
         }
       }
     }
+    if (has_next) prefetch_store<P, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], tid);
+    __syncthreads();
+    if (!has_next) break;
+    cur ^= 1;
+    t = tn;
+    geo = ngeo;
   }
 }
 
 template <int P, bool ADJ>
-__global__ __launch_bounds__(256) void m2l_f32_kernel(const float2 *__restrict__ X, const float2 *__restrict__ gbin,
-                                                      float2 *__restrict__ Y, float2 *__restrict__ bout,
-                                                      const float *__restrict__ bank, TileMap map) {
-  using B = F32Bank<P>;
-  constexpr int S = B::S, MT = B::MT, LS = B::LS;
-  __shared__ __attribute__((aligned(16))) float lx[4 * kRegBoxes * LS];
-  __shared__ float2 lgb[ADJ ? kRegBoxes : 1];
-
-  int level, tile;
-  tile_of(map, blockIdx.x, level, tile);
-  const int nside = 1 << level;
-  uint32_t tX, tY;
-  unmorton2(uint32_t(tile), tX, tY);
-  const int X0 = int(tX) * kTile, Y0 = int(tY) * kTile;
-  const int64_t off = level_off(level);
+__global__ __launch_bounds__(kThreads, 1) void m2l_f32_kernel(const float2 *__restrict__ X,
+                                                              const float2 *__restrict__ gbin, float2 *__restrict__ Y,
+                                                              float2 *__restrict__ bout,
+                                                              const float *__restrict__ bank, TileMap map,
+                                                              int ntiles) {
+  __shared__ __attribute__((aligned(16))) LdsF32<P, ADJ> sm;
   const int tid = threadIdx.x;
-
-  // Stage the 12x12 source block: lx[kk][box][q S + s] holds part q of
-  // coefficient k = S kk + s (q = 0: Re, 1: Im, 2: Re + Im); zero outside the grid.
-  for (int idx = tid; idx < kRegBoxes * P; idx += 256) {
-    const int rb = idx / P, k = idx - rb * P;
-    const int gx = X0 - kHalo + rb % kReg, gy = Y0 - kHalo + rb / kReg;
-    float2 v = make_float2(0.f, 0.f);
-    if (gx >= 0 && gy >= 0 && gx < nside && gy < nside) v = X[(off + morton2(gx, gy)) * P + k];
-    const int kk = k / S, s = k - kk * S;
-    float *d = lx + (kk * kRegBoxes + rb) * LS;
-    d[s] = v.x;
-    d[S + s] = v.y;
-    d[2 * S + s] = v.x + v.y;
-  }
-  if (ADJ) {
-    for (int rb = tid; rb < kRegBoxes; rb += 256) {
-      const int gx = X0 - kHalo + rb % kReg, gy = Y0 - kHalo + rb / kReg;
-      float2 v = make_float2(0.f, 0.f);
-      if (gbin && gx >= 0 && gy >= 0 && gx < nside && gy < nside) v = gbin[off + morton2(gx, gy)];
-      lgb[rb] = v;
-    }
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: class and half in SGPRs
+  if (int(blockIdx.x) >= ntiles) return;
+  {
+    Prefetch<P> pf;
+    const TileGeo g = tile_geo(map, blockIdx.x);
+    prefetch_issue<P, ADJ>(pf, g, X, gbin, tid);
+    prefetch_store<P, ADJ>(pf, sm.x[0], sm.gb[0], tid);
+    if (ADJ && tid == 0) sm.gb[1][kRegBoxes] = make_float2(0.f, 0.f);
   }
   __syncthreads();
-
-  const int wave = tid >> 6, lane = tid & 63;
-  F32Acc<P, ADJ> a;
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-    for (int q = 0; q < 3; ++q) a.t[mt][q] = f4_t{0.f, 0.f, 0.f, 0.f};
-  a.br = a.bi = a.s0r = a.s0i = a.gsr = a.gsi = 0.f;
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) a.gr[mt][i] = a.gi[mt][i] = 0.f;
-
+  // Every branch executes the same sequence of barriers (the tile loop is
+  // identical); the branch is uniform per wave.
   switch (wave) {
-    case 0: m2l_f32_class<P, ADJ, 0, 0>(lx, lgb, bank, lane, a); break;
-    case 1: m2l_f32_class<P, ADJ, 1, 0>(lx, lgb, bank, lane, a); break;
-    case 2: m2l_f32_class<P, ADJ, 0, 1>(lx, lgb, bank, lane, a); break;
-    default: m2l_f32_class<P, ADJ, 1, 1>(lx, lgb, bank, lane, a); break;
-  }
-
-  const int cx = wave & 1, cy = wave >> 1;
-  const int j = lane & 15, kk = lane >> 4;
-  const int gx = X0 + 2 * (j & 3) + cx, gy = Y0 + 2 * (j >> 2) + cy;
-  const bool valid = gx < nside && gy < nside;
-  const int64_t gbox = off + morton2(uint32_t(gx), uint32_t(gy));
-  const float logh = -float(level) * 0.69314718055994530942f;
-
-  if (!ADJ) {
-    // log row: sum the four k-groups of each box (lanes j, j+16, j+32, j+48)
-    float br = a.br, bi = a.bi;
-    br += __shfl_xor(br, 16);
-    bi += __shfl_xor(bi, 16);
-    br += __shfl_xor(br, 32);
-    bi += __shfl_xor(bi, 32);
-    if (bout && valid && kk == 0) bout[gbox] = make_float2(br + logh * a.s0r, bi + logh * a.s0i);
-  }
-  if (valid) {
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const int n0 = 16 * mt + 4 * kk;
-      if (n0 < P) {
-        float yr[4], yi[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float t1 = a.t[mt][0][i], t2 = a.t[mt][1][i], t3 = a.t[mt][2][i];
-          yr[i] = t1 - t2;
-          yi[i] = t3 - t1 - t2;
-          if (ADJ) {
-            yr[i] = a.gr[mt][i] - yr[i];
-            yi[i] = a.gi[mt][i] - yi[i];
-          }
-        }
-        if (ADJ && n0 == 0) {
-          yr[0] += logh * a.gsr;
-          yi[0] += logh * a.gsi;
-        }
-        float4 *dst = reinterpret_cast<float4 *>(Y + gbox * P + n0);
-        dst[0] = make_float4(yr[0], yi[0], yr[1], yi[1]);
-        dst[1] = make_float4(yr[2], yi[2], yr[3], yi[3]);
-      }
-    }
+    case 0: m2l_f32_run<P, ADJ, 0, 0, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+    case 1: m2l_f32_run<P, ADJ, 1, 0, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+    case 2: m2l_f32_run<P, ADJ, 0, 1, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+    case 3: m2l_f32_run<P, ADJ, 1, 1, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+    case 4: m2l_f32_run<P, ADJ, 0, 0, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+    case 5: m2l_f32_run<P, ADJ, 1, 0, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+    case 6: m2l_f32_run<P, ADJ, 0, 1, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+    default: m2l_f32_run<P, ADJ, 1, 1, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
   }
 }
 
+int num_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cached[dev] = v;
+  }
+  return cached[dev];
+}
+
+int launch_m2l_logrow_fwd(const float *M, float *b, int p, int lmin, int lmax, const void *ops, hipStream_t s);
+
 template <int P>
 static void launch_p(const float *M, const float *gb_in, float *L, float *b, const TileMap &map, int ntiles,
-                     bool adjoint, const void *ops, hipStream_t s) {
+                     int grid, bool adjoint, const void *ops, hipStream_t s) {
   const float2 *X = reinterpret_cast<const float2 *>(M);
   float2 *Y = reinterpret_cast<float2 *>(L);
   const float *bank = static_cast<const float *>(ops);
   if (adjoint)
-    hipLaunchKernelGGL((m2l_f32_kernel<P, true>), dim3(ntiles), dim3(256), 0, s, X,
-                       reinterpret_cast<const float2 *>(gb_in), Y, nullptr, bank, map);
+    hipLaunchKernelGGL((m2l_f32_kernel<P, true>), dim3(grid), dim3(kThreads), 0, s, X,
+                       reinterpret_cast<const float2 *>(gb_in), Y, nullptr, bank, map, ntiles);
   else
-    hipLaunchKernelGGL((m2l_f32_kernel<P, false>), dim3(ntiles), dim3(256), 0, s, X, nullptr, Y,
-                       reinterpret_cast<float2 *>(b), bank, map);
+    hipLaunchKernelGGL((m2l_f32_kernel<P, false>), dim3(grid), dim3(kThreads), 0, s, X, nullptr, Y,
+                       reinterpret_cast<float2 *>(b), bank, map, ntiles);
 }
 
 int launch_m2l_f32(const float *M, const float *gb_in, float *L, float *b, int depth, int p, int lmin, int lmax,
@@ -241,13 +487,17 @@ int launch_m2l_f32(const float *M, const float *gb_in, float *L, float *b, int d
   (void)depth;
   TileMap map = make_tile_map(lmin, lmax);
   const int ntiles = map.first[map.nlev];
+  const int grid = ntiles < num_cus() ? ntiles : num_cus();
   switch (p) {
-    case 8: launch_p<8>(M, gb_in, L, b, map, ntiles, adjoint, ops, s); break;
-    case 12: launch_p<12>(M, gb_in, L, b, map, ntiles, adjoint, ops, s); break;
-    case 16: launch_p<16>(M, gb_in, L, b, map, ntiles, adjoint, ops, s); break;
-    case 20: launch_p<20>(M, gb_in, L, b, map, ntiles, adjoint, ops, s); break;
+    case 8: launch_p<8>(M, gb_in, L, b, map, ntiles, grid, adjoint, ops, s); break;
+    case 12: launch_p<12>(M, gb_in, L, b, map, ntiles, grid, adjoint, ops, s); break;
+    case 16: launch_p<16>(M, gb_in, L, b, map, ntiles, grid, adjoint, ops, s); break;
+    case 20: launch_p<20>(M, gb_in, L, b, map, ntiles, grid, adjoint, ops, s); break;
   }
-  return check_launch(adjoint ? "m2l_backward (f32)" : "m2l (f32)");
+  int rc = check_launch(adjoint ? "m2l_backward (f32)" : "m2l (f32)");
+  if (rc == FMM2D_OK && !adjoint && b && (p % 16) == 0)  // no spare rows: separate log-row pass
+    rc = launch_m2l_logrow_fwd(M, b, p, lmin, lmax, ops, s);
+  return rc;
 }
 
 }  // namespace fmm2d

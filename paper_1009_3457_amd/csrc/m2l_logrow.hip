@@ -1,0 +1,84 @@
+// The log-potential row of the M2L for orders without spare MFMA rows
+// (p = 16): b(t) = sum_{o in O_c(t)} [ r_o . M~(t + o) + log(h) M~_0(t + o) ],
+// the constant term the complex logarithm adds to Eq. (eq:M2Lmat)'s local
+// expansion.  One workgroup per 8x8 target tile stages the 12x12 source block
+// and the 40 log rows in LDS; four lanes share a target box, each summing a
+// quarter of the k range over the box's 27 offsets, then reduce with lane
+// shuffles.  Vector-ALU work of 1/p of the M2L itself.
+#include "fmm2d_internal.h"
+#include "m2l_bank.h"
+#include "m2l_common.h"
+
+namespace fmm2d {
+
+template <int P>
+__global__ __launch_bounds__(256) void m2l_logrow_fwd_kernel(const float2 *__restrict__ X, float2 *__restrict__ bout,
+                                                             const float *__restrict__ bank, TileMap map) {
+  using B = F32Bank<P>;
+  constexpr int Q = P / 4;  // k values per lane
+  __shared__ float2 lx[kRegBoxes][P];
+  __shared__ float2 lr[kSlots][P];
+  const int tid = threadIdx.x;
+
+  int level, tile;
+  tile_of(map, blockIdx.x, level, tile);
+  const int nside = 1 << level;
+  uint32_t tX, tY;
+  unmorton2(uint32_t(tile), tX, tY);
+  const int X0 = int(tX) * kTile, Y0 = int(tY) * kTile;
+  const int64_t off = level_off(level);
+
+  const float2 *rsrc = reinterpret_cast<const float2 *>(bank + B::r_off);
+  for (int i = tid; i < kSlots * P; i += 256) lr[i / P][i % P] = rsrc[i];
+  for (int i = tid; i < kRegBoxes * P; i += 256) {
+    const int rb = i / P, k = i - rb * P;
+    const int gx = X0 - kHalo + rb % kReg, gy = Y0 - kHalo + rb / kReg;
+    float2 v = make_float2(0.f, 0.f);
+    if (gx >= 0 && gy >= 0 && gx < nside && gy < nside) v = X[(off + morton2(gx, gy)) * P + k];
+    lx[rb][k] = v;
+  }
+  __syncthreads();
+
+  const int box = tid >> 2, g = tid & 3;  // 64 target boxes x 4 k groups
+  const int tx = box & 7, ty = box >> 3;
+  const int sx = 1 - 2 * (tx & 1), sy = 1 - 2 * (ty & 1);
+  float br = 0.f, bi = 0.f, s0r = 0.f, s0i = 0.f;
+  for (int q = 0; q < 27; ++q) {
+    const int ox = sx * kOff00.ox[q], oy = sy * kOff00.oy[q];
+    const int rb = (ty + kHalo + oy) * kReg + (tx + kHalo + ox);
+    const float2 *r = lr[slot_of(ox, oy)];
+#pragma unroll
+    for (int e = 0; e < Q; ++e) {
+      const int k = g * Q + e;
+      const float2 m = lx[rb][k], rv = r[k];
+      br += rv.x * m.x - rv.y * m.y;
+      bi += rv.x * m.y + rv.y * m.x;
+    }
+    s0r += lx[rb][0].x;
+    s0i += lx[rb][0].y;
+  }
+  br += __shfl_xor(br, 1);
+  bi += __shfl_xor(bi, 1);
+  br += __shfl_xor(br, 2);
+  bi += __shfl_xor(bi, 2);
+  const int gx = X0 + tx, gy = Y0 + ty;
+  if (g == 0 && gx < nside && gy < nside) {
+    const float logh = -float(level) * 0.69314718055994530942f;
+    bout[off + morton2(uint32_t(gx), uint32_t(gy))] = make_float2(br + logh * s0r, bi + logh * s0i);
+  }
+}
+
+int launch_m2l_logrow_fwd(const float *M, float *b, int p, int lmin, int lmax, const void *ops, hipStream_t s) {
+  const TileMap map = make_tile_map(lmin, lmax);
+  const int ntiles = map.first[map.nlev];
+  const float2 *X = reinterpret_cast<const float2 *>(M);
+  float2 *bo = reinterpret_cast<float2 *>(b);
+  const float *bank = static_cast<const float *>(ops);
+  switch (p) {
+    case 16: hipLaunchKernelGGL(m2l_logrow_fwd_kernel<16>, dim3(ntiles), dim3(256), 0, s, X, bo, bank, map); break;
+    default: return set_error(FMM2D_EINVAL, "internal: log-row pass built for p = 16 only");
+  }
+  return check_launch("m2l log row");
+}
+
+}  // namespace fmm2d

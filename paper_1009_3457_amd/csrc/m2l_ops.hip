@@ -65,44 +65,50 @@ __global__ void f32_bank_kernel(float *bank) {
       int mt = int(r % B::MT);
       int slot = int(r / B::MT);
       int ox, oy;
-      if (pos < 3 * B::S && slot_used(slot, ox, oy)) {
+      if (pos < 2 * B::S && slot_used(slot, ox, oy)) {
         int part = pos / B::S, s = pos % B::S;
         int n = 16 * mt + lane % 16;
         int k = B::S * (lane / 16) + s;
-        if (n < P) {
-          cd a = m2l_entry(ox, oy, n, k);
-          double x = part == 0 ? a.re : (part == 1 ? a.im : a.re + a.im);
-          v = float(x);
-        }
+        cd a = {0.0, 0.0};
+        if (n < P) a = m2l_entry(ox, oy, n, k);
+        else if (B::kLogInRows && n == P) a = log_row_entry(double(-ox), double(-oy), k);
+        else if (B::kLogInRows && n == P + 1) a = {k == 0 ? 1.0 : 0.0, 0.0};
+        v = float(part == 0 ? a.re : a.im);
       }
     } else if (i >= B::r_off && i < B::r_off + B::r_floats) {
       size_t e = i - B::r_off;
       int ri = int(e % 2);
       size_t r = e / 2;
-      int s = int(r % B::S);
-      r /= B::S;
-      int kk = int(r % 4);
-      int slot = int(r / 4);
+      int k = int(r % P);
+      int slot = int(r / P);
       int ox, oy;
       if (slot_used(slot, ox, oy)) {
         // d = -o, negated as integers: a zero component must be +0 so that the
         // principal branch of log d is taken (arg d = +pi on the negative axis)
-        cd rv = log_row_entry(double(-ox), double(-oy), B::S * kk + s);
+        cd rv = log_row_entry(double(-ox), double(-oy), k);
         v = float(ri ? rv.im : rv.re);
       }
-    } else if (i >= B::ra_off && i < B::ra_off + B::ra_floats) {
-      size_t e = i - B::ra_off;
+    } else if (i >= B::ga_off && i < B::ga_off + B::ga_floats) {
+      size_t e = i - B::ga_off;
       int ri = int(e % 2);
       size_t r = e / 2;
-      int row = int(r % 16);
-      r /= 16;
+      int lane = int(r % 64);
+      r /= 64;
       int mt = int(r % B::MT);
-      int slot = int(r / B::MT);
-      int n = 16 * mt + row;
-      int ox, oy;
-      if (n < P && slot_used(slot, ox, oy)) {
-        cd rv = log_row_entry(double(ox), double(oy), n);
-        v = float(ri ? rv.im : rv.re);
+      r /= B::MT;
+      int g = int(r % B::kGbSteps);
+      int cls = int(r / B::kGbSteps);
+      int kappa = 4 * g + lane / 16;  // entry of the class's offset list
+      int n = 16 * mt + lane % 16;
+      if (kappa < 27) {
+        int ox = (1 - 2 * (cls & 1)) * kOff00.ox[kappa];
+        int oy = (1 - 2 * (cls >> 1)) * kOff00.oy[kappa];
+        if (n < P) {
+          cd rv = log_row_entry(double(ox), double(oy), n);  // row at d = +o
+          v = -float(ri ? rv.im : rv.re);
+        } else if (B::kGbSumRow && n == P + 2) {
+          v = ri ? 0.0f : -1.0f;
+        }
       }
     }
     bank[i] = v;
