@@ -9,21 +9,27 @@
 // child class of a tile share one list of 27 offsets; for each offset they
 // form the 16 columns of one product with a single operator (MFMA rows =
 // output orders n, 16 per M tile), run on v_mfma_f32_16x16x4_f32 in Gauss's
-// three-real-product form of the complex product (m2l_bank.h).  Two waves
-// own one class: wave (c, h) takes offsets 14h .. 14h + 13 of the class
-// list.  The reduction over the interaction list happens in the MFMA
-// accumulators in a fixed offset order; the second half's partial sums are
-// added to the first half's through LDS, always in that order, and each
-// L~(t) is written once, so results are bit-reproducible.
+// three-real-product form of the complex product (m2l_bank.h).  The
+// reduction over the interaction list happens in the MFMA accumulators in a
+// fixed offset order and each L~(t) is written once, so results are
+// bit-reproducible.
 //
-// The kernel is persistent: one workgroup of eight waves (two per SIMD) per
-// compute unit walks the tiles g, g + G, g + 2G, ...  A wave's class and
-// offsets never change, so for p <= 16 its 14 operator fragments are loaded
-// into registers once and reused for every tile; only source expansions
-// move.  The 12x12 source block of the next tile is fetched from HBM into
-// registers while the current tile is computed, then written to the second
-// of two LDS buffers.  For p = 20 (two M tiles) the fragments do not fit and
-// are streamed from the L2-resident bank one offset ahead.
+// The kernel is persistent: workgroups walk the tiles g, g + G, g + 2G, ...
+// A wave's class and offsets never change, so (p <= 16) its operator
+// fragments are loaded into registers once and reused for every tile; only
+// source expansions move.  The 12x12 source block of the next tile is fetched
+// from HBM while the current tile's products run and written to the second
+// of two LDS buffers.  Two shapes:
+//   * p <= 12: one wave per class holds all 27 operators; four-wave
+//     workgroups, two per compute unit, so one workgroup's tile epilogue runs
+//     under the other's matrix products;
+//   * p = 16, 20: two waves per class split the offset list 14 + 13 (eight-
+//     wave workgroups, one per compute unit) and add their partial sums
+//     through LDS, always first half + second half.  For p = 20 (two M tiles)
+//     the operators are streamed from the L2-resident bank one offset ahead.
+//
+// Classes (1, .) use the mirror image of class (0, .)'s offset list, so an
+// offset is (sx ox0, sy oy0) with signs fixed per wave.
 //
 // The log row b rides in spare MFMA rows when p is not a multiple of 16
 // (m2l_bank.h); for p = 16 it is computed by m2l_logrow.hip.
@@ -42,20 +48,48 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
 
-constexpr int kThreads = 512;  // 8 waves: class w & 3, offset half w >> 2
-constexpr int kHalf = 14;      // offsets per wave (14 and 13)
-constexpr int kGbHalf = 4;     // adjoint log-row k-steps of the first half (4 and 3)
-
 template <int P>
 struct F32Cfg {
   using B = F32Bank<P>;
   static constexpr int S = B::S, MT = B::MT, LS = B::LS;
-  static constexpr int NA = 2 * S;                          // floats of an A or B fragment (Re, Im)
-  static constexpr bool kRegBank = (MT == 1);               // operators held in registers
+  static constexpr int NA = 2 * S;                 // floats of an A or B fragment (Re, Im)
+  static constexpr bool kRegBank = (MT == 1);      // operators held in registers
   static constexpr bool kLogInRows = B::kLogInRows;
-  static constexpr int kChunks = kRegBoxes * P / 2;         // float4 chunks of a source block
+  static constexpr int WPC = (P <= 12) ? 1 : 2;    // waves per class
+  static constexpr int kThreads = 256 * WPC;
+  static constexpr int kWgPerCu = (WPC == 1) ? 2 : 1;
+  static constexpr int kChunks = kRegBoxes * P / 2;                // float4 chunks of a source block
   static constexpr int kPf = (kChunks + kThreads - 1) / kThreads;  // chunks per thread
-  static constexpr int kLdsX = 4 * kRegBoxes * LS;          // floats of one source buffer
+  static constexpr int kPfA = (WPC == 1) ? (kPf + 1) / 2 : kPf;  // chunks of the first fetch batch
+};
+
+// Offset-list slice and adjoint log-row k-steps of a wave.
+template <int P, int HALF>
+struct Slice {
+  static constexpr int WPC = F32Cfg<P>::WPC;
+  static constexpr int I0 = (WPC == 1) ? 0 : HALF * 14;
+  static constexpr int NI = (WPC == 1) ? 27 : (HALF ? 13 : 14);
+  static constexpr int G0 = (WPC == 1) ? 0 : HALF * 4;
+  static constexpr int NG = (WPC == 1) ? 7 : (HALF ? 3 : 4);
+};
+
+// Layout of a staged 12x12 source block in LDS, in 16-byte units.  The B
+// fragment of lane (kk, j) for one offset is NE units (2S floats: Re, Im of
+// k = S kk + s) of one box; the 16 lanes of a k-group read a 4x4 window of
+// same-class boxes (stride 2 in the region).  Boxes are therefore stored by
+// class: unit = kRow v' + 6 class + u' with (u', v') = (u, v) / 2, and
+// kRow = 28 = 12 (mod 16) makes the 16 units of any 4x4 window fall on 16
+// distinct 16-byte bank groups, so the reads are free of bank conflicts.
+template <int P>
+struct XLayout {
+  static constexpr int S = P / 4;
+  static constexpr int NE = (2 * S + 3) / 4;  // units per (k-group, box) record
+  static constexpr int kRow = 28;             // 4 classes x 6 + 4 spare units
+  static constexpr int kPlane = 6 * kRow;     // units per (k-group, unit index)
+  static constexpr int kFloats = 4 * NE * kPlane * 4;
+  __device__ static int unit(int kk, int e, int u, int v) {  // u, v in [0, 12)
+    return (kk * NE + e) * kPlane + kRow * (v >> 1) + 6 * ((u & 1) + 2 * (v & 1)) + (u >> 1);
+  }
 };
 
 // Source block of one tile held in registers between the global load and the
@@ -87,14 +121,16 @@ __device__ inline TileGeo tile_geo(const TileMap &map, int t) {
   return g;
 }
 
+// Loads chunks r0 .. r1-1 (and, with the first batch, the adjoint's gb).
 template <int P, bool ADJ>
 __device__ inline void prefetch_issue(Prefetch<P> &pf, const TileGeo &g, const float2 *__restrict__ X,
-                                      const float2 *__restrict__ gbin, int tid) {
+                                      const float2 *__restrict__ gbin, int tid, int r0, int r1) {
   using C = F32Cfg<P>;
-  pf.ok = 0;
+  if (r0 == 0) pf.ok = 0;
 #pragma unroll
   for (int r = 0; r < C::kPf; ++r) {
-    const int e = tid + kThreads * r;
+    if (r < r0 || r >= r1) continue;
+    const int e = tid + C::kThreads * r;
     const int rb = e / (P / 2), q = e - rb * (P / 2);
     const int gx = g.X0 - kHalo + rb % kReg, gy = g.Y0 - kHalo + rb / kReg;
     const bool in = e < C::kChunks && gx >= 0 && gy >= 0 && gx < g.nside && gy < g.nside;
@@ -102,7 +138,7 @@ __device__ inline void prefetch_issue(Prefetch<P> &pf, const TileGeo &g, const f
     pf.v[r] = *reinterpret_cast<const float4 *>(X + idx);
     pf.ok |= uint32_t(in) << r;
   }
-  if (ADJ && gbin) {  // gbin is uniform
+  if (ADJ && r0 == 0 && gbin) {  // gbin is uniform
     const int gx = g.X0 - kHalo + tid % kReg, gy = g.Y0 - kHalo + tid / kReg;
     const bool in = tid < kRegBoxes && gx >= 0 && gy >= 0 && gx < g.nside && gy < g.nside;
     pf.g = gbin[in ? g.off + morton2(uint32_t(gx), uint32_t(gy)) : 0];
@@ -110,16 +146,17 @@ __device__ inline void prefetch_issue(Prefetch<P> &pf, const TileGeo &g, const f
   }
 }
 
-// x[kk][box][q S + s] holds part q (0: Re, 1: Im) of coefficient k = S kk + s;
-// gb[box] the adjoint's log-row input (entry kRegBoxes stays zero).
+// Stores chunks r0 .. r1-1 into the XLayout buffer (and, with the first
+// batch, gb[box]; entry kRegBoxes of gb stays zero).
 template <int P, bool ADJ>
 __device__ inline void prefetch_store(const Prefetch<P> &pf, float *__restrict__ lx, float2 *__restrict__ lgb,
-                                      int tid) {
+                                      int tid, int r0, int r1) {
   using C = F32Cfg<P>;
-  constexpr int S = C::S, LS = C::LS;
+  constexpr int S = C::S;
 #pragma unroll
   for (int r = 0; r < C::kPf; ++r) {
-    const int e = tid + kThreads * r;
+    if (r < r0 || r >= r1) continue;
+    const int e = tid + C::kThreads * r;
     if (e < C::kChunks) {
       const int rb = e / (P / 2), q = e - rb * (P / 2);
       const bool in = (pf.ok >> r) & 1u;
@@ -129,13 +166,13 @@ __device__ inline void prefetch_store(const Prefetch<P> &pf, float *__restrict__
       for (int h = 0; h < 2; ++h) {
         const int k = 2 * q + h;
         const int kk = k / S, s = k - kk * S;
-        float *d = lx + (kk * kRegBoxes + rb) * LS;
-        d[s] = re[h];
-        d[S + s] = im[h];
+        const int u = rb % kReg, v = rb / kReg;
+        lx[XLayout<P>::unit(kk, s >> 2, u, v) * 4 + (s & 3)] = re[h];
+        lx[XLayout<P>::unit(kk, (S + s) >> 2, u, v) * 4 + ((S + s) & 3)] = im[h];
       }
     }
   }
-  if (ADJ && tid <= kRegBoxes)
+  if (ADJ && r0 == 0 && tid <= kRegBoxes)
     lgb[tid] = (tid < kRegBoxes && (pf.ok >> 31)) ? pf.g : make_float2(0.f, 0.f);
 }
 
@@ -143,12 +180,15 @@ template <int P, bool ADJ>
 struct LdsF32 {
   using C = F32Cfg<P>;
   static constexpr int MT = C::MT;
-  // partial sums of the second offset half: accumulators (+ sum of gb for p = 16)
+  // values one offset half hands to the other (two waves per class): the 3
+  // Gauss products of the 2 accumulator registers the other half writes out,
+  // per M tile, plus (adjoint) the second half's share of sum_o gb
   static constexpr bool kGbSumLanes = ADJ && !F32Bank<P>::kGbSumRow;
-  static constexpr int kN = MT * 12 + (kGbSumLanes ? 2 : 0);
-  float x[2][C::kLdsX];
+  static constexpr int kN = MT * 6 + (ADJ ? (kGbSumLanes ? 2 : 3) : 0);
+  static constexpr int kRed = (C::WPC == 2) ? 2 * 2 * 4 * kN * 64 : 1;  // [parity][half][class][value][lane]
+  float x[2][XLayout<P>::kFloats];
   float2 gb[2][ADJ ? kRegBoxes + 1 : 1];
-  float red[4][kN][64];
+  float red[kRed];
 };
 
 template <int P, bool ADJ, int CX, int CY, int HALF>
@@ -158,9 +198,10 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
                                             const TileMap &map, int ntiles, int tid) {
   using C = F32Cfg<P>;
   using B = F32Bank<P>;
-  constexpr int S = C::S, MT = C::MT, LS = C::LS, NA = C::NA;
-  constexpr int I0 = HALF * kHalf, NI = HALF ? 27 - kHalf : kHalf;
-  constexpr int G0 = HALF * kGbHalf, NG = HALF ? B::kGbSteps - kGbHalf : kGbHalf;
+  using XL = XLayout<P>;
+  using SL = Slice<P, HALF>;
+  constexpr int S = C::S, MT = C::MT, LS = C::LS, NA = C::NA, WPC = C::WPC;
+  constexpr int I0 = SL::I0, NI = SL::NI, G0 = SL::G0, NG = SL::NG;
   constexpr int kN = LdsF32<P, ADJ>::kN;
   constexpr bool kGbSumLanes = LdsF32<P, ADJ>::kGbSumLanes;
 
@@ -222,9 +263,20 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
     }
   }
 
-  const int lbase = (kk * kRegBoxes + (ty + kHalo) * kReg + (tx + kHalo)) * LS;
-  constexpr int dX = sx * LS, dY = sy * kReg * LS;
+  // this lane's unit in the staged block for offset (0, 0) minus the class
+  // part; per offset only a compile-time constant is added
+  const int lbase = (kk * XL::NE * XL::kPlane + XL::kRow * (j >> 2) + (j & 3)) * 4;
+  auto xoff = [&](int i) {  // compile-time after unrolling
+    const int ox = sx * kOff00.ox[I0 + i], oy = sy * kOff00.oy[I0 + i];
+    const int cu = CX + kHalo + ox, cv = CY + kHalo + oy;  // >= 0
+    return (XL::kRow * (cv >> 1) + 6 * ((cu & 1) + 2 * (cv & 1)) + (cu >> 1)) * 4;
+  };
   const float ln2 = 0.69314718055994530942f;
+  // The next tile's source block is fetched in two batches while this tile's
+  // products run; each batch is written to the other LDS buffer (released by
+  // every wave at the previous tile's barrier) a few offsets after its loads.
+  constexpr int kIssueA = 1, kStoreA = (WPC == 1) ? 12 : NI - 3;
+  constexpr int kIssueB = (WPC == 1) ? 13 : NI, kStoreB = (WPC == 1) ? 24 : NI;
 
   int t = blockIdx.x;
   TileGeo geo = tile_geo(map, t);
@@ -243,12 +295,12 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
     }
     const int tn = t + int(gridDim.x);
     const bool has_next = tn < ntiles;
-    TileGeo ngeo = geo;
+    const TileGeo ngeo = has_next ? tile_geo(map, tn) : geo;
     Prefetch<P> pf;
-    if (has_next) {
-      ngeo = tile_geo(map, tn);
-      prefetch_issue<P, ADJ>(pf, ngeo, X, gbin, tid);
-    }
+    // opaque copy of the thread index: the fetch addresses derived from it
+    // are recomputed where used instead of being kept live across the tile
+    int ftid = tid;
+    asm volatile("" : "+v"(ftid));
 
     const float *L = sm.x[cur];
     f4_t acc[MT][3];
@@ -261,11 +313,10 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
     constexpr int AM = C::kRegBank ? 1 : MT, AL = C::kRegBank ? 1 : LS;
     float acur[AM][AL], anxt[AM][AL];
     auto load_b = [&](float (&dst)[LS], int i) {
-      const float4 *bs =
-          reinterpret_cast<const float4 *>(L + lbase + kOff00.ox[I0 + i] * dX + kOff00.oy[I0 + i] * dY);
+      const float *bs = L + lbase + xoff(i);
 #pragma unroll
       for (int e = 0; e < LS / 4; ++e) {
-        const float4 v = bs[e];
+        const float4 v = *reinterpret_cast<const float4 *>(bs + e * XL::kPlane * 4);
         dst[4 * e] = v.x;
         dst[4 * e + 1] = v.y;
         dst[4 * e + 2] = v.z;
@@ -308,6 +359,12 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
           acc[mt][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b2, acc[mt][2], 0, 0, 0);
         }
       }
+      if (has_next) {
+        if (i == kIssueA) prefetch_issue<P, ADJ>(pf, ngeo, X, gbin, ftid, 0, C::kPfA);
+        if (i == kStoreA) prefetch_store<P, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], ftid, 0, C::kPfA);
+        if (i == kIssueB) prefetch_issue<P, ADJ>(pf, ngeo, X, gbin, ftid, C::kPfA, C::kPf);
+        if (i == kStoreB) prefetch_store<P, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], ftid, C::kPfA, C::kPf);
+      }
       // keep the software pipeline as written: operands of offset i+1 are
       // loaded during offset i, not hoisted further (register pressure)
       __builtin_amdgcn_sched_barrier(0);
@@ -319,6 +376,10 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
 #pragma unroll
           for (int e = 0; e < AL; ++e) acur[mt][e] = anxt[mt][e];
       }
+    }
+    if (has_next && kIssueB >= NI) {  // second batch not yet issued (short slices)
+      prefetch_issue<P, ADJ>(pf, ngeo, X, gbin, ftid, C::kPfA, C::kPf);
+      prefetch_store<P, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], ftid, C::kPfA, C::kPf);
     }
 
     // adjoint log-row part: k-steps over the offset list (B operand = gb)
@@ -341,45 +402,26 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
       }
     }
 
-    // ---- combine the two offset halves (fixed order: first + second)
-    float part[kN];
-    {
-      int n = 0;
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) part[n++] = acc[mt][q][e];
-      if (kGbSumLanes) {
-        part[n++] = gsr;
-        part[n++] = gsi;
-      }
-    }
-    if (HALF == 1) {
-#pragma unroll
-      for (int n = 0; n < kN; ++n) sm.red[cls][n][lane] = part[n];
-    }
-    __syncthreads();
-    if (HALF == 0) {
-#pragma unroll
-      for (int n = 0; n < kN; ++n) part[n] += sm.red[cls][n][lane];
-      const int gx = geo.X0 + tx, gy = geo.Y0 + ty;
-      const bool valid = gx < geo.nside && gy < geo.nside;
-      const int64_t gbox = geo.off + morton2(uint32_t(gx), uint32_t(gy));
-      const float logh = -float(geo.level) * ln2;
+    const int gx = geo.X0 + tx, gy = geo.Y0 + ty;
+    const bool valid = gx < geo.nside && gy < geo.nside;
+    const int64_t gbox = geo.off + morton2(uint32_t(gx), uint32_t(gy));
+    const float logh = -float(geo.level) * ln2;
+
+    if (WPC == 1) {
+      // ---- one wave per class: its accumulators are the whole sum.  The
+      // barrier only orders the LDS buffers (the next tile's block is
+      // complete; this tile's block is no longer read); the output follows.
+      __syncthreads();
       float sgr = 0.f, sgi = 0.f;  // adjoint: sum of gb over the list, for n = 0
       if (ADJ) {
-        if (kGbSumLanes) {  // each k-group holds part of the sum
-          sgr = part[MT * 12];
-          sgi = part[MT * 12 + 1];
-          sgr += __shfl_xor(sgr, 16);
-          sgi += __shfl_xor(sgi, 16);
+        if (kGbSumLanes) {
+          sgr = gsr + __shfl_xor(gsr, 16);
+          sgi = gsi + __shfl_xor(gsi, 16);
           sgr += __shfl_xor(sgr, 32);
           sgi += __shfl_xor(sgi, 32);
         } else {  // row p + 2 holds -sum gb: fetch it from the lane that owns it
           constexpr int row = P + 2, mtr = row / 16, kkr = (row % 16) / 4, er = row % 4;
-          const float t1 = part[mtr * 12 + er], t2 = part[mtr * 12 + 4 + er], t3 = part[mtr * 12 + 8 + er];
+          const float t1 = acc[mtr][0][er], t2 = acc[mtr][1][er], t3 = acc[mtr][2][er];
           sgr = -__shfl(t1 - t2, j + 16 * kkr);
           sgi = -__shfl(t3 - t1 - t2, j + 16 * kkr);
         }
@@ -391,13 +433,9 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
           float yr[4], yi[4];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const float t1 = part[mt * 12 + q], t2 = part[mt * 12 + 4 + q], t3 = part[mt * 12 + 8 + q];
-            yr[q] = t1 - t2;
-            yi[q] = t3 - t1 - t2;
-            if (ADJ) {
-              yr[q] = -yr[q];
-              yi[q] = -yi[q];
-            }
+            const float t1 = acc[mt][0][q], t2 = acc[mt][1][q], t3 = acc[mt][2][q];
+            yr[q] = ADJ ? t2 - t1 : t1 - t2;
+            yi[q] = ADJ ? t1 + t2 - t3 : t3 - t1 - t2;
           }
           if (n0 < P) {
             if (ADJ && n0 == 0) {
@@ -412,9 +450,80 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
           }
         }
       }
+    } else {
+      // ---- two waves per class: both publish their partial sums; then each
+      // writes half of the output rows (accumulator registers 2h, 2h + 1 of
+      // every lane), always adding first half + second half.  One barrier per
+      // tile: the partials are double buffered, and the source buffer read in
+      // this tile is rewritten only after the next tile's barrier.
+      float *red = sm.red + size_t(cur) * (2 * 4 * kN * 64);
+      float *pub = red + (HALF * 4 + cls) * kN * 64;
+      const float *oth = red + ((1 - HALF) * 4 + cls) * kN * 64;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int g = 0; g < 3; ++g)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) pub[((mt * 3 + g) * 2 + h) * 64 + lane] = acc[mt][g][2 * (1 - HALF) + h];
+      if (ADJ && HALF == 1) {
+        if (kGbSumLanes) {
+          pub[(MT * 6) * 64 + lane] = gsr;
+          pub[(MT * 6 + 1) * 64 + lane] = gsi;
+        } else {
+          constexpr int row = P + 2, mtr = row / 16, er = row % 4;
+#pragma unroll
+          for (int g = 0; g < 3; ++g) pub[(MT * 6 + g) * 64 + lane] = acc[mtr][g][er];
+        }
+      }
+      __syncthreads();
+      // combined Gauss product g of accumulator register 2 HALF + h (first + second half)
+      auto comb = [&](int mt, int g, int h) {
+        const float own = acc[mt][g][2 * HALF + h], other = oth[((mt * 3 + g) * 2 + h) * 64 + lane];
+        return HALF == 0 ? own + other : other + own;
+      };
+      float sgr = 0.f, sgi = 0.f;
+      if (ADJ && HALF == 0) {
+        if (kGbSumLanes) {
+          sgr = gsr + oth[(MT * 6) * 64 + lane];
+          sgi = gsi + oth[(MT * 6 + 1) * 64 + lane];
+          sgr += __shfl_xor(sgr, 16);
+          sgi += __shfl_xor(sgi, 16);
+          sgr += __shfl_xor(sgr, 32);
+          sgi += __shfl_xor(sgi, 32);
+        } else {
+          constexpr int row = P + 2, mtr = row / 16, kkr = (row % 16) / 4, er = row % 4;
+          const float t1 = acc[mtr][0][er] + oth[(MT * 6) * 64 + lane];
+          const float t2 = acc[mtr][1][er] + oth[(MT * 6 + 1) * 64 + lane];
+          const float t3 = acc[mtr][2][er] + oth[(MT * 6 + 2) * 64 + lane];
+          sgr = -__shfl(t1 - t2, j + 16 * kkr);
+          sgi = -__shfl(t3 - t1 - t2, j + 16 * kkr);
+        }
+      }
+      if (valid) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int n0 = 16 * mt + 4 * kk;  // rows n0 .. n0 + 3 live in this lane
+          if (n0 < P || (!ADJ && C::kLogInRows && HALF == 0 && n0 == P && bout)) {
+            float yr[2], yi[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const float t1 = comb(mt, 0, h), t2 = comb(mt, 1, h), t3 = comb(mt, 2, h);
+              yr[h] = ADJ ? t2 - t1 : t1 - t2;
+              yi[h] = ADJ ? t1 + t2 - t3 : t3 - t1 - t2;
+            }
+            if (n0 < P) {
+              if (ADJ && HALF == 0 && n0 == 0) {
+                yr[0] += logh * sgr;
+                yi[0] += logh * sgi;
+              }
+              *reinterpret_cast<float4 *>(Y + gbox * P + n0 + 2 * HALF) = make_float4(yr[0], yi[0], yr[1], yi[1]);
+            } else {  // rows p, p + 1: log row and the sum of M~_0
+              bout[gbox] = make_float2(yr[0] + logh * yr[1], yi[0] + logh * yi[1]);
+            }
+          }
+        }
+      }
     }
-    if (has_next) prefetch_store<P, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], tid);
-    __syncthreads();
     if (!has_next) break;
     cur ^= 1;
     t = tn;
@@ -423,11 +532,10 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
 }
 
 template <int P, bool ADJ>
-__global__ __launch_bounds__(kThreads, 1) void m2l_f32_kernel(const float2 *__restrict__ X,
-                                                              const float2 *__restrict__ gbin, float2 *__restrict__ Y,
-                                                              float2 *__restrict__ bout,
-                                                              const float *__restrict__ bank, TileMap map,
-                                                              int ntiles) {
+__global__ __launch_bounds__(F32Cfg<P>::kThreads, F32Cfg<P>::kWgPerCu) void m2l_f32_kernel(
+    const float2 *__restrict__ X, const float2 *__restrict__ gbin, float2 *__restrict__ Y, float2 *__restrict__ bout,
+    const float *__restrict__ bank, TileMap map, int ntiles) {
+  using C = F32Cfg<P>;
   __shared__ __attribute__((aligned(16))) LdsF32<P, ADJ> sm;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: class and half in SGPRs
@@ -435,22 +543,31 @@ __global__ __launch_bounds__(kThreads, 1) void m2l_f32_kernel(const float2 *__re
   {
     Prefetch<P> pf;
     const TileGeo g = tile_geo(map, blockIdx.x);
-    prefetch_issue<P, ADJ>(pf, g, X, gbin, tid);
-    prefetch_store<P, ADJ>(pf, sm.x[0], sm.gb[0], tid);
+    prefetch_issue<P, ADJ>(pf, g, X, gbin, tid, 0, C::kPf);
+    prefetch_store<P, ADJ>(pf, sm.x[0], sm.gb[0], tid, 0, C::kPf);
     if (ADJ && tid == 0) sm.gb[1][kRegBoxes] = make_float2(0.f, 0.f);
   }
   __syncthreads();
   // Every branch executes the same sequence of barriers (the tile loop is
   // identical); the branch is uniform per wave.
-  switch (wave) {
-    case 0: m2l_f32_run<P, ADJ, 0, 0, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
-    case 1: m2l_f32_run<P, ADJ, 1, 0, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
-    case 2: m2l_f32_run<P, ADJ, 0, 1, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
-    case 3: m2l_f32_run<P, ADJ, 1, 1, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
-    case 4: m2l_f32_run<P, ADJ, 0, 0, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
-    case 5: m2l_f32_run<P, ADJ, 1, 0, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
-    case 6: m2l_f32_run<P, ADJ, 0, 1, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
-    default: m2l_f32_run<P, ADJ, 1, 1, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+  if constexpr (C::WPC == 1) {
+    switch (wave) {
+      case 0: m2l_f32_run<P, ADJ, 0, 0, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+      case 1: m2l_f32_run<P, ADJ, 1, 0, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+      case 2: m2l_f32_run<P, ADJ, 0, 1, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+      default: m2l_f32_run<P, ADJ, 1, 1, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+    }
+  } else {
+    switch (wave) {
+      case 0: m2l_f32_run<P, ADJ, 0, 0, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+      case 1: m2l_f32_run<P, ADJ, 1, 0, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+      case 2: m2l_f32_run<P, ADJ, 0, 1, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+      case 3: m2l_f32_run<P, ADJ, 1, 1, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+      case 4: m2l_f32_run<P, ADJ, 0, 0, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+      case 5: m2l_f32_run<P, ADJ, 1, 0, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+      case 6: m2l_f32_run<P, ADJ, 0, 1, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+      default: m2l_f32_run<P, ADJ, 1, 1, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+    }
   }
 }
 
@@ -470,15 +587,18 @@ int launch_m2l_logrow_fwd(const float *M, float *b, int p, int lmin, int lmax, c
 
 template <int P>
 static void launch_p(const float *M, const float *gb_in, float *L, float *b, const TileMap &map, int ntiles,
-                     int grid, bool adjoint, const void *ops, hipStream_t s) {
+                     bool adjoint, const void *ops, hipStream_t s) {
+  using C = F32Cfg<P>;
+  const int slots = C::kWgPerCu * num_cus();
+  const int grid = ntiles < slots ? ntiles : slots;
   const float2 *X = reinterpret_cast<const float2 *>(M);
   float2 *Y = reinterpret_cast<float2 *>(L);
   const float *bank = static_cast<const float *>(ops);
   if (adjoint)
-    hipLaunchKernelGGL((m2l_f32_kernel<P, true>), dim3(grid), dim3(kThreads), 0, s, X,
+    hipLaunchKernelGGL((m2l_f32_kernel<P, true>), dim3(grid), dim3(C::kThreads), 0, s, X,
                        reinterpret_cast<const float2 *>(gb_in), Y, nullptr, bank, map, ntiles);
   else
-    hipLaunchKernelGGL((m2l_f32_kernel<P, false>), dim3(grid), dim3(kThreads), 0, s, X, nullptr, Y,
+    hipLaunchKernelGGL((m2l_f32_kernel<P, false>), dim3(grid), dim3(C::kThreads), 0, s, X, nullptr, Y,
                        reinterpret_cast<float2 *>(b), bank, map, ntiles);
 }
 
@@ -487,12 +607,11 @@ int launch_m2l_f32(const float *M, const float *gb_in, float *L, float *b, int d
   (void)depth;
   TileMap map = make_tile_map(lmin, lmax);
   const int ntiles = map.first[map.nlev];
-  const int grid = ntiles < num_cus() ? ntiles : num_cus();
   switch (p) {
-    case 8: launch_p<8>(M, gb_in, L, b, map, ntiles, grid, adjoint, ops, s); break;
-    case 12: launch_p<12>(M, gb_in, L, b, map, ntiles, grid, adjoint, ops, s); break;
-    case 16: launch_p<16>(M, gb_in, L, b, map, ntiles, grid, adjoint, ops, s); break;
-    case 20: launch_p<20>(M, gb_in, L, b, map, ntiles, grid, adjoint, ops, s); break;
+    case 8: launch_p<8>(M, gb_in, L, b, map, ntiles, adjoint, ops, s); break;
+    case 12: launch_p<12>(M, gb_in, L, b, map, ntiles, adjoint, ops, s); break;
+    case 16: launch_p<16>(M, gb_in, L, b, map, ntiles, adjoint, ops, s); break;
+    case 20: launch_p<20>(M, gb_in, L, b, map, ntiles, adjoint, ops, s); break;
   }
   int rc = check_launch(adjoint ? "m2l_backward (f32)" : "m2l (f32)");
   if (rc == FMM2D_OK && !adjoint && b && (p % 16) == 0)  // no spare rows: separate log-row pass
