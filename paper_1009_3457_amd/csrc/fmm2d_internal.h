@@ -98,6 +98,11 @@ int launch_m2l_ops(int p, int precision, void *ops, hipStream_t s);
 int launch_m2l_f32(const float *M, const float *gb_in, float *L, float *b, int depth, int p, int lmin, int lmax,
                    bool adjoint, const void *ops, hipStream_t s);
 bool m2l_mixed_supported(int p, int precision);
+int num_cus();  // compute units of the current device
+// b(t) for every box of levels lmin..lmax from the forward log rows r[slot][k]
+// (complex FP32, slot = (ox+3) + 7 (oy+3)); used when the MFMA tiles have no
+// spare rows for it
+int launch_m2l_logrow_fwd(const float *M, float *b, int p, int lmin, int lmax, const float *r, hipStream_t s);
 int launch_m2l_mixed(const float *M, const float *gb_in, float *L, float *b, int depth, int p, int lmin,
                      int lmax, bool adjoint, int precision, const void *ops, hipStream_t s);
 

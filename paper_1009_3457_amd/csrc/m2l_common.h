@@ -19,23 +19,24 @@ constexpr int kHalo = 2;                  // source halo on each side
 constexpr int kReg = kTile + 2 * kHalo;   // staged source block side (12)
 constexpr int kRegBoxes = kReg * kReg;    // 144
 
-// Maps a flat workgroup index to (level, tile-in-level).  Levels are laid out
-// deepest first.  Level l has max(1, 4^(l-3)) tiles; levels 2 (4x4 boxes)
-// uses one partially filled tile.
+// Maps a flat tile index to (level, tile-in-level).  Levels are laid out
+// deepest first.  With tiles of 2^shift x 2^shift boxes, level l has
+// max(1, 4^(l - shift)) tiles; a level smaller than one tile uses one
+// partially filled tile.
 struct TileMap {
   int nlev;
   int level[kMaxDepth + 1];
   int first[kMaxDepth + 2];  // first[i] = flat index of level[i]'s first tile; first[nlev] = total
 };
 
-inline TileMap make_tile_map(int lmin, int lmax) {
+inline TileMap make_tile_map(int lmin, int lmax, int shift = 3) {
   TileMap m{};
   int acc = 0;
   m.nlev = 0;
   for (int l = lmax; l >= lmin; --l) {
     m.level[m.nlev] = l;
     m.first[m.nlev] = acc;
-    acc += (l >= 3) ? (1 << (2 * (l - 3))) : 1;
+    acc += (l >= shift) ? (1 << (2 * (l - shift))) : 1;
     ++m.nlev;
   }
   m.first[m.nlev] = acc;

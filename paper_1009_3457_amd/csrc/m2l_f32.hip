@@ -583,8 +583,6 @@ int num_cus() {
   return cached[dev];
 }
 
-int launch_m2l_logrow_fwd(const float *M, float *b, int p, int lmin, int lmax, const void *ops, hipStream_t s);
-
 template <int P>
 static void launch_p(const float *M, const float *gb_in, float *L, float *b, const TileMap &map, int ntiles,
                      bool adjoint, const void *ops, hipStream_t s) {
@@ -615,7 +613,7 @@ int launch_m2l_f32(const float *M, const float *gb_in, float *L, float *b, int d
   }
   int rc = check_launch(adjoint ? "m2l_backward (f32)" : "m2l (f32)");
   if (rc == FMM2D_OK && !adjoint && b && (p % 16) == 0)  // no spare rows: separate log-row pass
-    rc = launch_m2l_logrow_fwd(M, b, p, lmin, lmax, ops, s);
+    rc = launch_m2l_logrow_fwd(M, b, p, lmin, lmax, static_cast<const float *>(ops) + F32Bank<16>::r_off, s);
   return rc;
 }
 

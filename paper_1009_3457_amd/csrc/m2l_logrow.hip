@@ -1,5 +1,6 @@
-// The log-potential row of the M2L for orders without spare MFMA rows
-// (p = 16): b(t) = sum_{o in O_c(t)} [ r_o . M~(t + o) + log(h) M~_0(t + o) ],
+// The log-potential row of the M2L for orders whose MFMA tiles have no spare
+// rows (p = 16 in FP32; p = 8, 16 in split precision):
+//   b(t) = sum_{o in O_c(t)} [ r_o . M~(t + o) + log(h) M~_0(t + o) ],
 // the constant term the complex logarithm adds to Eq. (eq:M2Lmat)'s local
 // expansion.  One workgroup per 8x8 target tile stages the 12x12 source block
 // and the 40 log rows in LDS; four lanes share a target box, each summing a
@@ -13,8 +14,7 @@ namespace fmm2d {
 
 template <int P>
 __global__ __launch_bounds__(256) void m2l_logrow_fwd_kernel(const float2 *__restrict__ X, float2 *__restrict__ bout,
-                                                             const float *__restrict__ bank, TileMap map) {
-  using B = F32Bank<P>;
+                                                             const float2 *__restrict__ rsrc, TileMap map) {
   constexpr int Q = P / 4;  // k values per lane
   __shared__ float2 lx[kRegBoxes][P];
   __shared__ float2 lr[kSlots][P];
@@ -28,7 +28,6 @@ __global__ __launch_bounds__(256) void m2l_logrow_fwd_kernel(const float2 *__res
   const int X0 = int(tX) * kTile, Y0 = int(tY) * kTile;
   const int64_t off = level_off(level);
 
-  const float2 *rsrc = reinterpret_cast<const float2 *>(bank + B::r_off);
   for (int i = tid; i < kSlots * P; i += 256) lr[i / P][i % P] = rsrc[i];
   for (int i = tid; i < kRegBoxes * P; i += 256) {
     const int rb = i / P, k = i - rb * P;
@@ -68,15 +67,16 @@ __global__ __launch_bounds__(256) void m2l_logrow_fwd_kernel(const float2 *__res
   }
 }
 
-int launch_m2l_logrow_fwd(const float *M, float *b, int p, int lmin, int lmax, const void *ops, hipStream_t s) {
+int launch_m2l_logrow_fwd(const float *M, float *b, int p, int lmin, int lmax, const float *r, hipStream_t s) {
   const TileMap map = make_tile_map(lmin, lmax);
   const int ntiles = map.first[map.nlev];
   const float2 *X = reinterpret_cast<const float2 *>(M);
   float2 *bo = reinterpret_cast<float2 *>(b);
-  const float *bank = static_cast<const float *>(ops);
+  const float2 *rs = reinterpret_cast<const float2 *>(r);
   switch (p) {
-    case 16: hipLaunchKernelGGL(m2l_logrow_fwd_kernel<16>, dim3(ntiles), dim3(256), 0, s, X, bo, bank, map); break;
-    default: return set_error(FMM2D_EINVAL, "internal: log-row pass built for p = 16 only");
+    case 8: hipLaunchKernelGGL(m2l_logrow_fwd_kernel<8>, dim3(ntiles), dim3(256), 0, s, X, bo, rs, map); break;
+    case 16: hipLaunchKernelGGL(m2l_logrow_fwd_kernel<16>, dim3(ntiles), dim3(256), 0, s, X, bo, rs, map); break;
+    default: return set_error(FMM2D_EINVAL, "internal: log-row pass built for p = 8, 16 only");
   }
   return check_launch("m2l log row");
 }

@@ -115,14 +115,131 @@ __global__ void f32_bank_kernel(float *bank) {
   }
 }
 
-size_t m2l_ops_bytes(int p, int precision) {
-  if (!p_supported(p)) return 0;
-  if (precision == FMM2D_F32) return f32_bank_bytes(p);
-  if (m2l_mixed_supported(p, precision)) return mixed_bank_bytes(p, precision);
+// ---------------------------------------------------- split-precision bank --
+// Entry of the interleaved real embedding of a complex value (m2l_mixed_bank.h).
+__device__ inline double embed(cd a, int pr, int pc) {
+  return pr == 0 ? (pc == 0 ? a.re : -a.im) : (pc == 0 ? a.im : a.re);
+}
+
+template <int PREC>
+__device__ inline uint16_t round16(double v) {
+  if constexpr (PREC == FMM2D_BF16X3) return __builtin_bit_cast(uint16_t, __bf16(float(v)));
+  else return __builtin_bit_cast(uint16_t, _Float16(float(v)));
+}
+
+template <int PREC>
+__device__ inline double widen16(uint16_t h) {
+  if constexpr (PREC == FMM2D_BF16X3) return double(float(__builtin_bit_cast(__bf16, h)));
+  else return double(float(__builtin_bit_cast(_Float16, h)));
+}
+
+// hi (part 0) or lo (part 1) of the two-term split of v
+template <int PREC>
+__device__ inline uint16_t split16(double v, int part) {
+  const uint16_t hi = round16<PREC>(v);
+  return part == 0 ? hi : round16<PREC>(v - widen16<PREC>(hi));
+}
+
+template <int P, int PREC>
+__global__ void mixed_bank_kernel(unsigned char *bank) {
+  using B = MixedBank<P>;
+  using C = MixCfg<P>;
+  constexpr int R = C::R;
+  uint16_t *h = reinterpret_cast<uint16_t *>(bank);
+  const size_t n16 = B::r_off / 2;  // sections a and ga with their padding
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n16; i += stride) {
+    uint16_t out = 0;
+    const size_t byte = 2 * i;
+    if (byte < B::a_off + B::a_bytes) {
+      size_t e16 = i - B::a_off / 2;
+      const int e = int(e16 % 8), lane = int((e16 / 8) % 64);
+      size_t rest = e16 / 512;
+      const int ks = int(rest % C::KS);
+      rest /= C::KS;
+      const int mt = int(rest % C::MT), slot = int(rest / C::MT);
+      const int rho = 16 * mt + lane % 16, kap = 32 * ks + 8 * (lane / 16) + e;
+      const int seg = kap / R, c = kap % R;
+      int ox, oy;
+      if (seg < 3 && slot_used(slot, ox, oy)) {
+        double v = 0.0;
+        if (rho < R) {
+          v = embed(m2l_entry(ox, oy, rho / 2, c / 2), rho % 2, c % 2);
+        } else if (C::kLogRows && rho < R + 2) {
+          v = embed(log_row_entry(double(-ox), double(-oy), c / 2), rho - R, c % 2);
+        } else if (C::kLogRows && rho < R + 4) {
+          v = (c == rho - R - 2) ? 1.0 : 0.0;  // Re / Im of M~_0
+        }
+        out = split16<PREC>(v, seg == 2 ? 1 : 0);
+      }
+    } else if (byte >= B::ga_off && byte < B::ga_off + B::ga_bytes) {
+      size_t e16 = i - B::ga_off / 2;
+      const int e = int(e16 % 8), lane = int((e16 / 8) % 64);
+      size_t rest = e16 / 512;
+      const int t = int(rest % 2);
+      rest /= 2;
+      const int mt = int(rest % C::MT);
+      rest /= C::MT;
+      const int part = int(rest % 2), cls = int(rest / 2);
+      const int rho = 16 * mt + lane % 16, kap = 32 * t + 8 * (lane / 16) + e;
+      const int q = kap / 2, pc = kap % 2;  // entry of the class's offset list, Re / Im of gb
+      if (q < 27 && rho < R) {
+        const int ox = (1 - 2 * (cls & 1)) * kOff00.ox[q];
+        const int oy = (1 - 2 * (cls >> 1)) * kOff00.oy[q];
+        const cd rv = log_row_entry(double(ox), double(oy), rho / 2);  // row at d = +o
+        out = split16<PREC>(-embed(rv, rho % 2, pc), part);
+      }
+    }
+    h[i] = out;
+  }
+  float *r = reinterpret_cast<float *>(bank + B::r_off);
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < size_t(kSlots) * P * 2; i += stride) {
+    const int ri = int(i % 2), k = int((i / 2) % P), slot = int(i / 2 / P);
+    int ox, oy;
+    float v = 0.f;
+    if (slot_used(slot, ox, oy)) {
+      const cd rv = log_row_entry(double(-ox), double(-oy), k);
+      v = float(ri ? rv.im : rv.re);
+    }
+    r[i] = v;
+  }
+}
+
+size_t mixed_bank_bytes(int p, int precision) {
+  if (precision != FMM2D_BF16X3 && precision != FMM2D_F16X3) return 0;
+  switch (p) {
+    case 8: return MixedBank<8>::total_bytes;
+    case 12: return MixedBank<12>::total_bytes;
+    case 16: return MixedBank<16>::total_bytes;
+    case 20: return MixedBank<20>::total_bytes;
+  }
   return 0;
 }
 
-int launch_mixed_ops(int p, int precision, void *ops, hipStream_t s);
+template <int PREC>
+static void launch_mixed_bank(int p, unsigned char *bank, hipStream_t s) {
+  dim3 grid(512), block(256);
+  switch (p) {
+    case 8: hipLaunchKernelGGL((mixed_bank_kernel<8, PREC>), grid, block, 0, s, bank); break;
+    case 12: hipLaunchKernelGGL((mixed_bank_kernel<12, PREC>), grid, block, 0, s, bank); break;
+    case 16: hipLaunchKernelGGL((mixed_bank_kernel<16, PREC>), grid, block, 0, s, bank); break;
+    case 20: hipLaunchKernelGGL((mixed_bank_kernel<20, PREC>), grid, block, 0, s, bank); break;
+  }
+}
+
+int launch_mixed_ops(int p, int precision, void *ops, hipStream_t s) {
+  unsigned char *bank = static_cast<unsigned char *>(ops);
+  if (precision == FMM2D_BF16X3) launch_mixed_bank<FMM2D_BF16X3>(p, bank, s);
+  else launch_mixed_bank<FMM2D_F16X3>(p, bank, s);
+  return check_launch("m2l split-precision operator bank");
+}
+
+size_t m2l_ops_bytes(int p, int precision) {
+  if (!p_supported(p)) return 0;
+  if (precision == FMM2D_F32) return f32_bank_bytes(p);
+  return mixed_bank_bytes(p, precision);
+  return 0;
+}
 
 int launch_m2l_ops(int p, int precision, void *ops, hipStream_t s) {
   if (precision != FMM2D_F32) return launch_mixed_ops(p, precision, ops, s);

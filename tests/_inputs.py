@@ -2,6 +2,8 @@
 
 Only the seeded generators (synthetic) and the oracle are used here; nothing
 comes from the GPU library."""
+import functools
+
 import numpy as np
 
 import oracle
@@ -36,3 +38,9 @@ def rel(a, b):
     b = np.asarray(b)
     den = np.linalg.norm(b.ravel())
     return float(np.linalg.norm((a - b).ravel()) / (den if den > 0 else 1.0))
+
+
+@functools.lru_cache(maxsize=3)
+def full_size_multipoles(depth: int, p: int, n: int, kind: str):
+    """multipoles() of the large workloads, computed once per test session."""
+    return multipoles(depth, p, n, seed=3, kind=kind)

@@ -108,10 +108,13 @@ def test_null_pointers_rejected_on_host():
     assert lib.fmm2d_p2p(FAKE, FAKE, FAKE, FAKE, FAKE, -5, 8, FAKE, FAKE, None) == -1
 
 
-def test_mixed_precision_reported_unsupported_when_not_built():
+def test_split_precision_banks_are_built_for_every_order():
     lib = _lib()
     for prec in (1, 2):
-        for p in (8, 12, 16, 20):
-            if lib.fmm2d_m2l_operators_bytes(p, prec) == 0:
-                rc = lib.fmm2d_m2l(FAKE, ctypes.c_void_p(0x2000), None, 8, p, 2, 8, prec, FAKE, 1 << 30, None)
-                assert rc == -2
+        sizes = [lib.fmm2d_m2l_operators_bytes(p, prec) for p in (8, 12, 16, 20)]
+        assert all(s > 0 for s in sizes) and sizes == sorted(sizes)
+        assert lib.fmm2d_m2l_operators_bytes(10, prec) == 0
+        # a bank one byte short is refused before any device work
+        need = lib.fmm2d_m2l_operators_bytes(16, prec)
+        rc = lib.fmm2d_m2l(FAKE, ctypes.c_void_p(0x2000), None, 9, 16, 2, 9, prec, FAKE, need - 1, None)
+        assert rc == -5

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests._inputs import level_slices, multipoles, rel
+from tests._inputs import full_size_multipoles, level_slices, multipoles, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -116,6 +116,25 @@ def test_m2l_f32_full_size_c2_sampled(P, kind):
         Lr_s = Lr * h ** (np.arange(p) + 1.0)[None, :]
         got = L[sl][boxes]
         assert rel(got, Lr_s) < TOL_F32, (l, rel(got, Lr_s))
+        assert rel(b[sl][boxes], br) < TOL_F32
+
+
+@pytest.mark.parametrize("depth,p,n", [(9, 16, 1 << 22), (10, 20, 1 << 24)])
+def test_m2l_f32_full_size_sampled_large(P, depth, p, n):
+    """The 2^22-point depth-9 p = 16 and 2^24-point depth-10 p = 20 workloads
+    (half clustered, half uniform) in FP32, sampled boxes of every level."""
+    print(f"m2l f32 full size depth={depth} p={p}", flush=True)
+    Ms32, M_exact = full_size_multipoles(depth, p, n, "mixed")
+    L, b = _run_m2l(P, Ms32, depth, p)
+    g = np.random.Generator(np.random.PCG64(79))
+    for l, sl in level_slices(depth):
+        ns = 1 << l
+        cand = [(0, 0), (ns - 1, ns - 1), (0, ns - 1), (ns - 1, 0), (2, ns // 2), (ns // 2, ns - 3)]
+        cand += [tuple(v) for v in g.integers(0, ns, size=(40, 2))]
+        boxes = np.array(sorted({oracle.morton(int(x), int(y), l) for x, y in cand}), np.int64)
+        Lr, br = oracle.m2l_boxes(M_exact[sl], l, p, boxes)
+        Lr_s = Lr * (2.0 ** -l) ** (np.arange(p) + 1.0)[None, :]
+        assert rel(L[sl][boxes], Lr_s) < TOL_F32, (l, rel(L[sl][boxes], Lr_s))
         assert rel(b[sl][boxes], br) < TOL_F32
 
 
