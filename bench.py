@@ -1,16 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the M2L translation (Sec. 4.1) on one MI355X.
 
-A step is one M2L + fused reduction over every box of levels 2..depth (the
-whole interaction-list schedule, contraction and reduction), on expansions
-already resident in HBM; the operator bank is generated once per p before
-timing, as the operators depend only on p.  The default workload is N = 2^20
-uniform points, quadtree depth 8, p = 12, FP32.
+A step is one M2L with its fused reduction over every box of levels 2..depth:
+the whole interaction-list schedule, contraction and reduction, run on
+expansions already resident in HBM. The operator bank is generated once per
+(p, precision) before timing, because the operators depend only on p.
 
-Prints one JSON line with translations/s (exact, boundary-truncated count),
-the 8p^2-flop Gop/s, the roofline of the M2L kernel measured with HIP events
-on the stream it runs on, the adjoint's time, and the FP64 oracle's rate on
-the host cores.
+The default workload is N = 2^20 uniform points, quadtree depth 8, p = 12,
+FP32, with b (the log-potential constant, carried in spare MFMA rows).
+
+Prints one JSON line with:
+  * translations/s, using the exact, boundary-truncated count;
+  * Gop/s, at 8p^2 flops per translation;
+  * the roofline of the M2L kernel, timed with HIP events on its stream;
+  * the adjoint's time;
+  * split precision against FP32: the same step in BF16x3 and FP16x3 on this
+    workload and on the 2^22-point, depth-9, p = 16 one;
+  * the FP64 oracle's rate on the host cores.
 """
 from __future__ import annotations
 
@@ -25,15 +31,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# name -> (points, depth, p, point set, precision)
+# name -> (points, depth, p, point set, default precision, outputs)
+# outputs "Lb": the local expansions and b; "L": the local expansions only (the
+# M2L of Eq. (eq:M2Lmat); at p = 16 b needs a separate pass)
 WORKLOADS = {
-    "m2l_uniform_n1M_d8_p12": (1 << 20, 8, 12, "uniform", "f32"),
-    "m2l_mixed_n4M_d9_p16": (1 << 22, 9, 16, "mixed", "f32"),
-    "m2l_mixed_n16M_d10_p20": (1 << 24, 10, 20, "mixed", "f32"),
-    "m2l_uniform_n4k_d4_p8": (4096, 4, 8, "uniform", "f32"),
+    "m2l_uniform_n1M_d8_p12": (1 << 20, 8, 12, "uniform", "f32", "Lb"),
+    "m2l_mixed_n4M_d9_p16": (1 << 22, 9, 16, "mixed", "f32", "L"),
+    "m2l_mixed_n16M_d10_p20": (1 << 24, 10, 20, "mixed", "f32", "L"),
+    "m2l_uniform_n4k_d4_p8": (4096, 4, 8, "uniform", "f32", "Lb"),
 }
 DEFAULT = "m2l_uniform_n1M_d8_p12"
-PEAK_FP32_MFMA_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
+MIXED_COMPARE = ["m2l_uniform_n1M_d8_p12", "m2l_mixed_n4M_d9_p16"]
+PEAK_TFLOPS = {"f32": 157.3, "bf16x3": 2500.0, "f16x3": 2500.0}  # MI355X dense MFMA, per dtype
+MFMA_FLOPS_FACTOR = {"f32": 1, "bf16x3": 3, "f16x3": 3}           # split products per real product
 PEAK_HBM_GBS = 8000.0
 PAPER_P12_TRANS_PER_S = 80.05e6  # Tesla C1060, p = 12, depth-8 tree (Table tab:m2ltesla)
 
@@ -43,7 +53,7 @@ def m2l_kernel_sources(precision="f32"):
     c = os.path.join(ROOT, "paper_1009_3457_amd", "csrc")
     names = ["m2l_f32.hip", "m2l_bank.h", "m2l_common.h", "fmm2d_internal.h"]
     if precision != "f32":
-        names = ["m2l_mixed.hip", "m2l_mixed_bank.h", "m2l_common.h", "fmm2d_internal.h"]
+        names = ["m2l_mixed.hip", "m2l_mixed_bank.h", "m2l_bank.h", "m2l_common.h", "fmm2d_internal.h"]
     return [os.path.join(c, n) for n in names]
 
 
@@ -75,14 +85,13 @@ def _points(kind, n, seed):
 
 
 def cpu_baseline(Ms_np, depth, p, budget_s=12.0, max_runs=200):
-    """The FP64 oracle's M2L (operator built per translation from Eq.
-    (eq:M2Lmat)) over all levels 2..depth, timed on the host cores; repeated
-    while the time budget allows (at least once), median reported."""
-    import numpy as np
+    """The FP64 oracle's M2L over all levels 2..depth, timed on the host cores.
 
+    The oracle builds the operator per translation from Eq. (eq:M2Lmat). The
+    run is repeated while the time budget allows (at least once) and the median
+    is reported."""
     import oracle
-    M = oracle.unscale_multipoles(Ms_np.astype(np.complex128), depth)
-    ntrans = None
+    M = oracle.unscale_multipoles(Ms_np.astype("complex128"), depth)
     times = []
     t_start = time.perf_counter()
     while len(times) < max_runs:
@@ -100,6 +109,118 @@ def cpu_baseline(Ms_np, depth, p, budget_s=12.0, max_runs=200):
                       f"median of {len(times)} runs ({med:.3f} s each)"}
 
 
+class Workload:
+    """Points -> tree -> P2M -> M2M on the GPU; the multipole expansions stay
+    resident in HBM for the timed M2L launches."""
+
+    def __init__(self, name, seed, dev):
+        import torch
+
+        import paper_1009_3457_amd as P
+        import synthetic as sy
+        self.name = name
+        self.n, self.depth, self.p, self.kind, self.default_prec, self.outputs = WORKLOADS[name]
+        xy = torch.from_numpy(_points(self.kind, self.n, seed)).to(dev)
+        q = torch.from_numpy(sy.charges(self.n, seed + 1)).to(dev)
+        perm, ls = P.build_tree(xy, self.depth)
+        xs, qs = P.gather(xy, perm), P.gather(q, perm)
+        self.M = P.m2m(P.p2m(xs, qs, ls, self.depth, self.p), self.depth, self.p)
+        nb = P.num_boxes(self.depth)
+        self.L = torch.zeros(nb, self.p, dtype=torch.complex64, device=dev)
+        self.b = torch.zeros(nb, dtype=torch.complex64, device=dev) if self.outputs == "Lb" else None
+        self.gM = torch.zeros(nb, self.p, dtype=torch.complex64, device=dev)
+        self.gb = torch.zeros(nb, dtype=torch.complex64, device=dev) if self.outputs == "Lb" else None
+        self.dev = dev
+        self.ntrans = P.translation_count(2, self.depth)
+        torch.cuda.synchronize(dev)
+
+    def time_m2l(self, prec_name, steps, warmup):
+        """(forward ms, adjoint ms) per launch: HIP events recorded on the
+        stream the kernels are launched on, around `steps` back-to-back calls
+        of the C ABI."""
+        import torch
+
+        import paper_1009_3457_amd as P
+        from paper_1009_3457_amd import _binding as B
+        prec = B.PRECISIONS[prec_name]
+        ops = P.m2l_operators(self.p, prec, self.dev)
+        lib = B.load()
+        stream = torch.cuda.current_stream(self.dev)
+        sp, vp = ctypes.c_void_p(stream.cuda_stream), ctypes.c_void_p
+        ptr = lambda t: vp(t.data_ptr()) if t is not None else None  # noqa: E731
+        fwd_args = (ptr(self.M), ptr(self.L), ptr(self.b), self.depth, self.p, 2, self.depth, prec,
+                    ptr(ops), ops.numel(), sp)
+        bwd_args = (ptr(self.L), ptr(self.gb), ptr(self.gM), self.depth, self.p, 2, self.depth, prec,
+                    ptr(ops), ops.numel(), sp)
+
+        def timed(fn, fargs, k, w):
+            for _ in range(w):
+                if fn(*fargs) != 0:
+                    raise RuntimeError(lib.fmm2d_last_error().decode())
+            torch.cuda.synchronize(self.dev)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            rc = 0
+            for _ in range(k):
+                rc |= fn(*fargs)
+            e1.record(stream)
+            torch.cuda.synchronize(self.dev)
+            if rc != 0:
+                raise RuntimeError(lib.fmm2d_last_error().decode())
+            return e0.elapsed_time(e1) / k
+
+        ms_fwd = timed(lib.fmm2d_m2l, fwd_args, steps, warmup)
+        ms_bwd = timed(lib.fmm2d_m2l_backward, bwd_args, max(steps // 2, 1), max(warmup // 2, 1))
+        return ms_fwd, ms_bwd
+
+    def level_rel_diff(self, ref_L):
+        """max over levels of ||L - ref_L||_F / ||ref_L||_F (device arithmetic)."""
+        import torch
+
+        import paper_1009_3457_amd as P
+        worst = 0.0
+        for l in range(2, self.depth + 1):
+            a, b = P.level_offset(l), P.level_offset(l + 1)
+            den = torch.linalg.vector_norm(ref_L[a:b]).item()
+            num = torch.linalg.vector_norm(self.L[a:b] - ref_L[a:b]).item()
+            worst = max(worst, num / den if den > 0 else num)
+        return worst
+
+
+def roofline(w, prec_name, ms):
+    flops = 8.0 * w.p * w.p * w.ntrans * MFMA_FLOPS_FACTOR[prec_name]
+    tflops = flops / (ms * 1e-3) / 1e12
+    boxes = sum(4 ** l for l in range(2, w.depth + 1))
+    alg_bytes = boxes * w.p * 8 * 2 + (boxes * 8 if w.outputs == "Lb" else 0)
+    peak = PEAK_TFLOPS[prec_name]
+    return {"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s", "frac": tflops / peak,
+            "traffic": recorded_traffic(w.name, prec_name),
+            "algorithmic_bytes": alg_bytes,
+            "hbm_frac": alg_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+
+
+def mixed_comparison(seed, dev, steps, warmup, main=None):
+    """FP32 against BF16x3 and FP16x3 on the same inputs: time per launch,
+    speedup, and the largest per-level relative difference from the FP32
+    result.  The error against FP64 is checked by the parity tests."""
+    out = {}
+    for name in MIXED_COMPARE:
+        w = main if (main is not None and main.name == name) else Workload(name, seed, dev)
+        f_ms, f_bwd = w.time_m2l("f32", steps, warmup)
+        ref = w.L.clone()
+        rec = {"outputs": w.outputs, "f32_ms": f_ms, "f32_adjoint_ms": f_bwd}
+        for prec in ("bf16x3", "f16x3"):
+            ms, bwd = w.time_m2l(prec, steps, warmup)
+            rec[prec] = {"ms": ms, "adjoint_ms": bwd, "speedup_vs_f32": f_ms / ms,
+                         "adjoint_speedup_vs_f32": f_bwd / bwd,
+                         "max_level_rel_diff_vs_f32": w.level_rel_diff(ref),
+                         "roofline_frac": roofline(w, prec, ms)["frac"]}
+        out[name] = rec
+    out["tolerance_vs_fp64"] = {"f32": 1e-5, "bf16x3": 1e-4, "f16x3": 1e-4}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +229,7 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["f32", "bf16x3", "f16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision comparison")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy, 4 times (reference for "
@@ -129,72 +251,17 @@ def main():
                                    "device's share is measured at --gpus 1"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
-
-    import paper_1009_3457_amd as P
-    import synthetic as sy
-    from paper_1009_3457_amd import _binding as B
-
-    n, depth, p, kind, prec_name = WORKLOADS[args.workload]
-    prec_name = args.precision or prec_name
-    prec = B.PRECISIONS[prec_name]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    # inputs resident in HBM: points -> tree -> P2M -> M2M on the GPU
-    xy = torch.from_numpy(_points(kind, n, args.seed)).to(dev)
-    q = torch.from_numpy(sy.charges(n, args.seed + 1)).to(dev)
-    perm, ls = P.build_tree(xy, depth)
-    xs, qs = P.gather(xy, perm), P.gather(q, perm)
-    M = P.m2m(P.p2m(xs, qs, ls, depth, p), depth, p)
-    ops = P.m2l_operators(p, prec, dev)
-    nb = P.num_boxes(depth)
-    L = torch.zeros(nb, p, dtype=torch.complex64, device=dev)
-    b = torch.zeros(nb, dtype=torch.complex64, device=dev)
-    gM = torch.zeros(nb, p, dtype=torch.complex64, device=dev)
-    torch.cuda.synchronize(dev)
-
-    lib = B.load()
-    stream = torch.cuda.current_stream(dev)
-    sp = ctypes.c_void_p(stream.cuda_stream)
-    vp = ctypes.c_void_p
-    fwd_args = (vp(M.data_ptr()), vp(L.data_ptr()), vp(b.data_ptr()), depth, p, 2, depth, prec,
-                vp(ops.data_ptr()), ops.numel(), sp)
-    bwd_args = (vp(L.data_ptr()), vp(b.data_ptr()), vp(gM.data_ptr()), depth, p, 2, depth, prec,
-                vp(ops.data_ptr()), ops.numel(), sp)
-    fwd, bwd = lib.fmm2d_m2l, lib.fmm2d_m2l_backward
-
-    def timed(fn, fargs, steps, warmup):
-        for _ in range(warmup):
-            if fn(*fargs) != 0:
-                raise RuntimeError(lib.fmm2d_last_error().decode())
-        torch.cuda.synchronize(dev)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        rc = 0
-        for _ in range(steps):
-            rc |= fn(*fargs)
-        e1.record(stream)
-        torch.cuda.synchronize(dev)
-        if rc != 0:
-            raise RuntimeError(lib.fmm2d_last_error().decode())
-        return e0.elapsed_time(e1) / steps  # ms per launch
-
-    # the timed region: K forward M2L steps, bracketed by synchronisation
-    ms_fwd = timed(fwd, fwd_args, args.steps, args.warmup)
-    ms_bwd = timed(bwd, bwd_args, max(args.steps // 2, 1), max(args.warmup // 2, 1))
-
-    ntrans = P.translation_count(2, depth)
-    padded = 27 * sum(4 ** l for l in range(2, depth + 1))
-    flops = 8.0 * p * p * ntrans
-    tflops = flops / (ms_fwd * 1e-3) / 1e12
-    boxes = sum(4 ** l for l in range(2, depth + 1))
-    alg_bytes = boxes * p * 8 * 2 + boxes * 8  # read M~, write L~ and b (complex64)
-    value = ntrans / (ms_fwd * 1e-3)
-
-    traffic = recorded_traffic(args.workload, prec_name)
+    w = Workload(args.workload, args.seed, dev)
+    prec_name = args.precision or w.default_prec
+    # the timed region: K forward M2L launches, bracketed by synchronisation
+    ms_fwd, ms_bwd = w.time_m2l(prec_name, args.steps, args.warmup)
+    value = w.ntrans / (ms_fwd * 1e-3)
+    padded = 27 * sum(4 ** l for l in range(2, w.depth + 1))
+    default_run = args.workload == DEFAULT and args.precision is None
 
     out = {
         "metric": "M2L Gop/s & translations/s (N=2^20, p=12), % of roofline; mixed vs FP32 at tol",
@@ -206,25 +273,26 @@ def main():
         "ms_per_step": ms_fwd,
         "higher_is_better": True,
         "scaling": "weak",
-        "vs_baseline": value / PAPER_P12_TRANS_PER_S if (depth, p) == (8, 12) else None,
-        "dtype": "f32" if prec_name == "f32" else prec_name,
+        # the paper's p = 12 figure on the same tree (another machine: context, not the target)
+        "vs_baseline": value / PAPER_P12_TRANS_PER_S if (w.depth, w.p, prec_name) == (8, 12, "f32") else None,
+        "dtype": prec_name,
         "data": "synthetic",
-        "config": {"workload": args.workload, "points": n, "point_set": kind, "depth": depth,
-                   "p": p, "levels": f"2..{depth}", "precision": prec_name,
-                   "translations": ntrans, "padded_translations": padded},
-        "gop_s": flops / (ms_fwd * 1e-3) / 1e9,
-        "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP32_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": tflops / PEAK_FP32_MFMA_TFLOPS,
-                     "traffic": traffic,
-                     "algorithmic_bytes": alg_bytes,
-                     "hbm_frac": alg_bytes / (ms_fwd * 1e-3) / 1e9 / PEAK_HBM_GBS},
+        "config": {"workload": args.workload, "points": w.n, "point_set": w.kind, "depth": w.depth,
+                   "p": w.p, "levels": f"2..{w.depth}", "precision": prec_name, "outputs": w.outputs,
+                   "translations": w.ntrans, "padded_translations": padded, "seed": args.seed},
+        "gop_s": 8.0 * w.p * w.p * w.ntrans / (ms_fwd * 1e-3) / 1e9,
+        "roofline": roofline(w, prec_name, ms_fwd),
         "adjoint_ms": ms_bwd,
-        "adjoint_translations_per_s": ntrans / (ms_bwd * 1e-3),
+        "adjoint_translations_per_s": w.ntrans / (ms_bwd * 1e-3),
+        "adjoint_roofline_frac": roofline(w, prec_name, ms_bwd)["frac"],
         "paper_context": {"translations_per_s": PAPER_P12_TRANS_PER_S, "gop_s": 511.06,
                           "hardware": "Tesla C1060, FP32, p=12, 2,359,152 translations"},
     }
+    if default_run and not args.no_mixed:
+        out["mixed_vs_f32"] = mixed_comparison(args.seed, dev, max(args.steps // 2, 10),
+                                               max(args.warmup // 2, 2), main=w)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(M.cpu().numpy(), depth, p)
+        out["cpu_baseline"] = cpu_baseline(w.M.cpu().numpy(), w.depth, w.p)
     print(json.dumps(out))
 
 
