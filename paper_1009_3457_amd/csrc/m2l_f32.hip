@@ -347,15 +347,28 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
         load_b(bnxt, i + 1);
         load_a(anxt, i + 1);
       }
+      // the loads above stay ahead of this offset's products (the scheduler
+      // would otherwise sink them next to their first use)
+      __builtin_amdgcn_sched_barrier(0);
+      // each accumulator takes a chain of S products (chained accumulation
+      // issues faster than rotating accumulators)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           const float a0 = C::kRegBank ? areg[i][s] : acur[mt % AM][s % AL];
+          acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bcur[s], acc[mt][0], 0, 0, 0);
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const float a1 = C::kRegBank ? areg[i][S + s] : acur[mt % AM][(S + s) % AL];
+          acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bcur[S + s], acc[mt][1], 0, 0, 0);
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const float a0 = C::kRegBank ? areg[i][s] : acur[mt % AM][s % AL];
           const float a1 = C::kRegBank ? areg[i][S + s] : acur[mt % AM][(S + s) % AL];
           const float a2 = a0 + a1, b2 = bcur[s] + bcur[S + s];  // third Gauss operands
-          acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bcur[s], acc[mt][0], 0, 0, 0);
-          acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bcur[S + s], acc[mt][1], 0, 0, 0);
           acc[mt][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b2, acc[mt][2], 0, 0, 0);
         }
       }

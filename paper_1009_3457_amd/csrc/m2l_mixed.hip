@@ -52,12 +52,18 @@ constexpr int kMRow = 40;                    // units per row of same-class boxe
 template <int P>
 struct MixK {
   using C = MixCfg<P>;
-  static constexpr int NT = 4;  // N tiles (16 boxes each) per wave: the 64 boxes of one class
-  static constexpr int kThreads = 256;
-  static constexpr int kItems = (kMRegBoxes * C::NPL + kThreads - 1) / kThreads;  // staging items per thread
-  static constexpr int kPlanes = 2 * C::NPL;                                       // hi chunks, lo chunks
+  static constexpr int kHalves = 1;  // compute waves per class (2 doubles the operator fetches: slower)
+  static constexpr int NT = 4 / kHalves;  // N tiles (16 boxes each) per compute wave; a class has 4
+  static constexpr int kCompute = 4 * kHalves;  // compute waves: kHalves per class
+  static constexpr int kLoaders = 4;            // loader waves: stage the next tile's source block
+  static constexpr int kThreads = 64 * (kCompute + kLoaders);
+  static constexpr int kLThreads = 64 * kLoaders;
+  static constexpr int kItems = (kMRegBoxes * C::NPL + kLThreads - 1) / kLThreads;  // staging items per loader thread
+  static constexpr int kPlanes = 2 * C::NPL;                                        // hi chunks, lo chunks
+  static constexpr int kPlaneUnits = kPlanes * kMPlane;
   static constexpr int kApf = (P <= 16) ? 2 : 1;  // operator prefetch distance (offsets)
   static constexpr bool kBpf = (P <= 16);          // source fragments loaded one offset ahead
+  static constexpr int kMid = 12;                  // FP16x3: offset after which the mid-tile barrier sits
   // operator prefetch runs on into the next tile, except where the adjoint's
   // log-row part needs those registers (p = 20)
   template <bool ADJ>
@@ -65,18 +71,19 @@ struct MixK {
 };
 
 // 16-byte unit of plane pl for block box (u, v), u, v in [0, 20).  Boxes are
-// grouped by class; within a class, rows of 10 units with a row stride of 40
-// (= 8 mod 16), so the 16 lanes of a lane group, which read an 8 x 2 window
-// of same-class boxes, hit 16 distinct 16-byte bank groups.
+// grouped by class; within a class, rows of 10 units with a row stride of 40.
 __device__ constexpr int munit(int pl, int u, int v) {
   return pl * kMPlane + kMRow * (v >> 1) + 10 * ((u & 1) + 2 * (v & 1)) + (u >> 1);
 }
 
+// Two staging buffers: the loader waves fill one while the compute waves
+// read the other.
 template <int P, bool ADJ>
 struct LdsMix {
-  u32x4_t x[MixK<P>::kPlanes * kMPlane];
-  float2 gb[ADJ ? kMRegBoxes + 1 : 1];  // entry kMRegBoxes stays zero
-  float wmax[4];
+  u32x4_t x[2][MixK<P>::kPlaneUnits];
+  float2 gb[2][ADJ ? kMRegBoxes + 1 : 1];  // entry kMRegBoxes stays zero
+  float wmax[MixK<P>::kLoaders];
+  int scale[2];  // FP16x3: the block is stored times 2^scale
 };
 
 template <int PREC>
@@ -142,11 +149,110 @@ __device__ inline int round_tile(int r, int b, int G) {
   return r * G + pos;
 }
 
-template <int P, int PREC, bool ADJ, int CX, int CY>
-__device__ __forceinline__ void m2l_mixed_run(LdsMix<P, ADJ> &sm, const float2 *__restrict__ X,
-                                              const float2 *__restrict__ gbin, float2 *__restrict__ Y,
-                                              float2 *__restrict__ bout, const unsigned char *__restrict__ bank,
-                                              const TileMap &map, int ntiles, int tid) {
+// ------------------------------------------------------------ loader waves --
+// Stages tile t's 20x20 source block (and, adjoint, gb) into buffer `buf`:
+// load FP32, (FP16: scale by the block's power of two), split into hi / lo,
+// store.  FP16x3 runs one workgroup barrier between finding the block's
+// largest magnitude and storing (the compute waves run the matching one
+// inside their offset loop); `active` false only takes that barrier.
+template <int P, int PREC, bool ADJ>
+__device__ __forceinline__ void mixed_stage(LdsMix<P, ADJ> &sm, int buf, bool active, const MGeo &geo,
+                                            const float2 *__restrict__ X, const float2 *__restrict__ gbin, int ltid) {
+  using C = MixCfg<P>;
+  using K = MixK<P>;
+  constexpr int NPL = C::NPL;
+  constexpr bool kF16 = (PREC == FMM2D_F16X3);
+  float4 v[K::kItems][2];
+  uint32_t ok = 0;
+  float2 gv[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+  if (active) {
+#pragma unroll
+    for (int it = 0; it < K::kItems; ++it) {
+      const int e = ltid + K::kLThreads * it;
+      const int rb = e / NPL, q = e - rb * NPL;
+      const int gx = geo.X0 - kHalo + rb % kMReg, gy = geo.Y0 - kHalo + rb / kMReg;
+      const bool in = e < kMRegBoxes * NPL && gx >= 0 && gy >= 0 && gx < geo.nside && gy < geo.nside;
+      const int64_t idx = in ? (geo.off + morton2(uint32_t(gx), uint32_t(gy))) * P + 4 * q : 0;
+      v[it][0] = *reinterpret_cast<const float4 *>(X + idx);
+      v[it][1] = *reinterpret_cast<const float4 *>(X + idx + 2);
+      ok |= uint32_t(in) << it;
+    }
+    if (ADJ && gbin) {
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        const int e = ltid + K::kLThreads * it;
+        const int gx = geo.X0 - kHalo + e % kMReg, gy = geo.Y0 - kHalo + e / kMReg;
+        const bool in = e < kMRegBoxes && gx >= 0 && gy >= 0 && gx < geo.nside && gy < geo.nside;
+        const float2 w = gbin[in ? geo.off + morton2(uint32_t(gx), uint32_t(gy)) : 0];
+        gv[it] = in ? w : make_float2(0.f, 0.f);
+      }
+    }
+  }
+  int sc = 0;
+  if (kF16) {
+    float m = 0.f;
+#pragma unroll
+    for (int it = 0; it < K::kItems; ++it)
+      if ((ok >> it) & 1u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          m = fmaxf(m, fmaxf(fmaxf(fabsf(v[it][h].x), fabsf(v[it][h].y)), fmaxf(fabsf(v[it][h].z), fabsf(v[it][h].w))));
+    if (ADJ)
+#pragma unroll
+      for (int it = 0; it < 2; ++it) m = fmaxf(m, fmaxf(fabsf(gv[it].x), fabsf(gv[it].y)));
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) m = fmaxf(m, __shfl_xor(m, d));
+    if ((ltid & 63) == 0) sm.wmax[ltid >> 6] = m;
+    __syncthreads();  // the mid-tile barrier
+#pragma unroll
+    for (int w = 0; w < K::kLoaders; ++w) m = fmaxf(m, sm.wmax[w]);
+    sc = (m > 0.f) ? 14 - ilogbf(m) : 0;
+    if (ltid == 0 && active) sm.scale[buf] = sc;
+  }
+  if (!active) return;
+#pragma unroll
+  for (int it = 0; it < K::kItems; ++it) {
+    const int e = ltid + K::kLThreads * it;
+    if (e < kMRegBoxes * NPL) {
+      const int rb = e / NPL, q = e - rb * NPL;
+      const bool in = (ok >> it) & 1u;
+      float w[8] = {v[it][0].x, v[it][0].y, v[it][0].z, v[it][0].w, v[it][1].x, v[it][1].y, v[it][1].z, v[it][1].w};
+#pragma unroll
+      for (int c = 0; c < 8; ++c) w[c] = in ? (kF16 ? ldexpf(w[c], sc) : w[c]) : 0.f;
+      u32x4_t hi, lo;
+      split8<PREC>(w, hi, lo);
+      const int u = rb % kMReg, vv = rb / kMReg;
+      sm.x[buf][munit(q, u, vv)] = hi;
+      sm.x[buf][munit(NPL + q, u, vv)] = lo;
+    }
+  }
+  if (ADJ) {
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int e = ltid + K::kLThreads * it;
+      if (e < kMRegBoxes) sm.gb[buf][e] = kF16 ? make_float2(ldexpf(gv[it].x, sc), ldexpf(gv[it].y, sc)) : gv[it];
+    }
+  }
+}
+
+template <int P, int PREC, bool ADJ>
+__device__ __forceinline__ void mixed_loader(LdsMix<P, ADJ> &sm, const float2 *__restrict__ X,
+                                             const float2 *__restrict__ gbin, const TileMap &map, int ntiles,
+                                             int ltid) {
+  const int G = int(gridDim.x), b = int(blockIdx.x);
+  for (int r = 0, t = round_tile(0, b, G); t < ntiles; t = round_tile(++r, b, G)) {
+    const int tn = round_tile(r + 1, b, G);
+    const bool has_next = tn < ntiles;
+    mixed_stage<P, PREC, ADJ>(sm, (r + 1) & 1, has_next, mgeo(map, has_next ? tn : t), X, gbin, ltid);
+    __syncthreads();  // end of round r
+  }
+}
+
+// ----------------------------------------------------------- compute waves --
+template <int P, int PREC, bool ADJ, int CX, int CY, int H>
+__device__ __forceinline__ void mixed_compute(LdsMix<P, ADJ> &sm, float2 *__restrict__ Y, float2 *__restrict__ bout,
+                                              const unsigned char *__restrict__ bank, const TileMap &map, int ntiles,
+                                              int tid) {
   using C = MixCfg<P>;
   using K = MixK<P>;
   using B = MixedBank<P>;
@@ -155,7 +261,7 @@ __device__ __forceinline__ void m2l_mixed_run(LdsMix<P, ADJ> &sm, const float2 *
   constexpr bool kF16 = (PREC == FMM2D_F16X3);
   constexpr int cls = CX + 2 * CY;
   constexpr int sx = 1 - 2 * CX, sy = 1 - 2 * CY;  // mirror of class (0, 0)'s offsets
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63;
   const int j = lane & 15, g = lane >> 4;
 
   const __amdgpu_buffer_rsrc_t rsrc =
@@ -165,8 +271,8 @@ __device__ __forceinline__ void m2l_mixed_run(LdsMix<P, ADJ> &sm, const float2 *
     return __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rsrc, alane, int(byte_off), 0));
   };
 
-  // LDS byte address of this lane's B chunk for k-step ks at window (0, 0);
-  // per offset and N tile only an immediate is added
+  // LDS byte address (within a buffer) of this lane's B chunk for k-step ks
+  // at window (0, 0); per offset and N tile only an immediate is added
   int abase[KS];
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
@@ -174,14 +280,11 @@ __device__ __forceinline__ void m2l_mixed_run(LdsMix<P, ADJ> &sm, const float2 *
     const int pl = seg >= 3 ? 0 : ((seg == 1) ? NPL : 0) + q % NPL;  // zero chunk: any finite data (A is 0)
     abase[ks] = (pl * kMPlane + kMRow * (j >> 3) + (j & 7)) * 16;
   }
-  auto bimm = [&](int i, int nt) {  // compile-time after unrolling
+  auto bimm = [&](int i, int nt) {  // compile-time after unrolling; this wave's N tile nt is NT H + nt
     const int ox = sx * kOff00.ox[i], oy = sy * kOff00.oy[i];
-    return (2 * kMRow * nt + kMRow * ((CY + kHalo + oy) >> 1) + 10 * (((CX + ox) & 1) + 2 * ((CY + oy) & 1)) +
+    return (2 * kMRow * (NT * H + nt) + kMRow * ((CY + kHalo + oy) >> 1) + 10 * (((CX + ox) & 1) + 2 * ((CY + oy) & 1)) +
             ((CX + kHalo + ox) >> 1)) *
            16;
-  };
-  auto lds16 = [&](int byte_off) {
-    return *reinterpret_cast<const u32x4_t *>(reinterpret_cast<const char *>(sm.x) + byte_off);
   };
 
   // adjoint: gb entries q = 16 t + 4 g + e of the class's list, as indices
@@ -218,85 +321,17 @@ __device__ __forceinline__ void m2l_mixed_run(LdsMix<P, ADJ> &sm, const float2 *
   if (kCarryA)
 #pragma unroll
     for (int i = 0; i < kApf; ++i) load_a(i, i);
+  if (kF16) __syncthreads();  // the prologue's mid-tile barrier (loader waves stage tile 0)
+  __syncthreads();            // tile 0 is staged
 
   const float ln2 = 0.69314718055994530942f;
-  const int G = int(gridDim.x);
-  for (int r = 0, t = round_tile(0, int(blockIdx.x), G); t < ntiles; t = round_tile(++r, int(blockIdx.x), G)) {
+  const int G = int(gridDim.x), bidx = int(blockIdx.x);
+  for (int r = 0, t = round_tile(0, bidx, G); t < ntiles; t = round_tile(++r, bidx, G)) {
     const MGeo geo = mgeo(map, t);
-
-    // ---------------- stage the source block: load, (scale,) split, store
-    float4 v[K::kItems][2];
-    uint32_t ok = 0;
-#pragma unroll
-    for (int it = 0; it < K::kItems; ++it) {
-      const int e = tid + K::kThreads * it;
-      const int rb = e / NPL, q = e - rb * NPL;
-      const int gx = geo.X0 - kHalo + rb % kMReg, gy = geo.Y0 - kHalo + rb / kMReg;
-      const bool in = e < kMRegBoxes * NPL && gx >= 0 && gy >= 0 && gx < geo.nside && gy < geo.nside;
-      const int64_t idx = in ? (geo.off + morton2(uint32_t(gx), uint32_t(gy))) * P + 4 * q : 0;
-      v[it][0] = *reinterpret_cast<const float4 *>(X + idx);
-      v[it][1] = *reinterpret_cast<const float4 *>(X + idx + 2);
-      ok |= uint32_t(in) << it;
-    }
-    float2 gv[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-    if (ADJ && gbin) {
-#pragma unroll
-      for (int it = 0; it < 2; ++it) {
-        const int e = tid + K::kThreads * it;
-        const int gx = geo.X0 - kHalo + e % kMReg, gy = geo.Y0 - kHalo + e / kMReg;
-        const bool in = e < kMRegBoxes && gx >= 0 && gy >= 0 && gx < geo.nside && gy < geo.nside;
-        const float2 w = gbin[in ? geo.off + morton2(uint32_t(gx), uint32_t(gy)) : 0];
-        gv[it] = in ? w : make_float2(0.f, 0.f);
-      }
-    }
-    int sc = 0;  // FP16: values are stored times 2^sc
-    float m = 0.f;
-    if (kF16) {
-#pragma unroll
-      for (int it = 0; it < K::kItems; ++it)
-        if ((ok >> it) & 1u)
-#pragma unroll
-          for (int h = 0; h < 2; ++h)
-            m = fmaxf(m, fmaxf(fmaxf(fabsf(v[it][h].x), fabsf(v[it][h].y)), fmaxf(fabsf(v[it][h].z), fabsf(v[it][h].w))));
-      if (ADJ)
-#pragma unroll
-        for (int it = 0; it < 2; ++it) m = fmaxf(m, fmaxf(fabsf(gv[it].x), fabsf(gv[it].y)));
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) m = fmaxf(m, __shfl_xor(m, d));
-    }
-    __syncthreads();  // every wave is done with the previous tile's block
-    if (kF16) {
-      if (lane == 0) sm.wmax[wave] = m;
-      __syncthreads();
-      m = fmaxf(fmaxf(sm.wmax[0], sm.wmax[1]), fmaxf(sm.wmax[2], sm.wmax[3]));
-      sc = (m > 0.f) ? 14 - ilogbf(m) : 0;
-    }
-#pragma unroll
-    for (int it = 0; it < K::kItems; ++it) {
-      const int e = tid + K::kThreads * it;
-      if (e < kMRegBoxes * NPL) {
-        const int rb = e / NPL, q = e - rb * NPL;
-        const bool in = (ok >> it) & 1u;
-        float w[8] = {v[it][0].x, v[it][0].y, v[it][0].z, v[it][0].w,
-                      v[it][1].x, v[it][1].y, v[it][1].z, v[it][1].w};
-#pragma unroll
-        for (int c = 0; c < 8; ++c) w[c] = in ? (kF16 ? ldexpf(w[c], sc) : w[c]) : 0.f;
-        u32x4_t hi, lo;
-        split8<PREC>(w, hi, lo);
-        const int u = rb % kMReg, vv = rb / kMReg;
-        sm.x[munit(q, u, vv)] = hi;
-        sm.x[munit(NPL + q, u, vv)] = lo;
-      }
-    }
-    if (ADJ) {
-#pragma unroll
-      for (int it = 0; it < 2; ++it) {
-        const int e = tid + K::kThreads * it;
-        if (e < kMRegBoxes)
-          sm.gb[e] = kF16 ? make_float2(ldexpf(gv[it].x, sc), ldexpf(gv[it].y, sc)) : gv[it];
-      }
-    }
-    __syncthreads();
+    const int buf = r & 1;
+    const char *xb = reinterpret_cast<const char *>(sm.x[buf]);
+    auto lds16 = [&](int byte_off) { return *reinterpret_cast<const u32x4_t *>(xb + byte_off); };
+    const int sc = kF16 ? sm.scale[buf] : 0;
 
     // ---------------- products over the 27 offsets of the class
     f4_t acc[MT][NT];
@@ -305,37 +340,69 @@ __device__ __forceinline__ void m2l_mixed_run(LdsMix<P, ADJ> &sm, const float2 *
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-    u32x4_t Bf[2][NT][KS];
-    auto load_b = [&](int i, int pos) {
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-          if (C::b_src(ks) == ks) Bf[pos][nt][ks] = lds16(abase[ks] + bimm(i, nt));
-    };
     if (!kCarryA)
 #pragma unroll
       for (int i = 0; i < kApf; ++i) load_a(i, i);
-    if (K::kBpf) load_b(0, 0);
+    if constexpr (K::kBpf) {
+      // source fragments of a whole offset, one offset ahead
+      u32x4_t Bf[2][NT][KS];
+      auto load_b = [&](int i, int pos) {
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-      const int cur = K::kBpf ? (i & 1) : 0;
-      if (K::kBpf) {
-        if (i + 1 < 27) load_b(i + 1, cur ^ 1);
-      } else {
-        load_b(i, 0);
-      }
-      if (kCarryA || i + kApf < 27) load_a((i + kApf) % 27, (i + kApf) % kRing);  // next tile restarts at 0
-      const int ap = i % kRing;
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+        for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
           for (int ks = 0; ks < KS; ++ks)
-            if (C::a_chunk(ks, 0) >= 0 || C::a_chunk(ks, 1) >= 0 || C::a_chunk(ks, 2) >= 0 || C::a_chunk(ks, 3) >= 0)
+            if (C::b_src(ks) == ks) Bf[pos][nt][ks] = lds16(abase[ks] + bimm(i, nt));
+      };
+      load_b(0, 0);
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        const int cur = i & 1;
+        if (i + 1 < 27) load_b(i + 1, cur ^ 1);
+        if (kCarryA || i + kApf < 27) load_a((i + kApf) % 27, (i + kApf) % kRing);  // next tile restarts at 0
+        // the loads above stay ahead of this offset's products (the
+        // scheduler would otherwise sink them next to their first use)
+        __builtin_amdgcn_sched_barrier(0);
+        const int ap = i % kRing;
+        // k-steps innermost: each accumulator takes a chain of KS products
+        // (chained accumulation issues faster than rotating accumulators)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
               acc[mt][nt] = mfma16<PREC>(A[ap][mt][C::a_src(ks)], Bf[cur][nt][C::b_src(ks)], acc[mt][nt]);
-      __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (kF16 && i == K::kMid) __syncthreads();  // matches the loader waves' mid-tile barrier
+      }
+    } else {
+      // source fragments of one N tile, one N tile ahead (fewer registers)
+      u32x4_t Bn[2][KS];
+      auto load_bn = [&](int i, int nt, int pos) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+          if (C::b_src(ks) == ks) Bn[pos][ks] = lds16(abase[ks] + bimm(i, nt));
+      };
+      load_bn(0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        if (kCarryA || i + kApf < 27) load_a((i + kApf) % 27, (i + kApf) % kRing);  // next tile restarts at 0
+        const int ap = i % kRing;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int pos = (i * NT + nt) & 1;
+          if (nt + 1 < NT) load_bn(i, nt + 1, pos ^ 1);
+          else if (i + 1 < 27) load_bn(i + 1, 0, pos ^ 1);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+              acc[mt][nt] = mfma16<PREC>(A[ap][mt][C::a_src(ks)], Bn[pos][C::b_src(ks)], acc[mt][nt]);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if (kF16 && i == K::kMid) __syncthreads();  // matches the loader waves' mid-tile barrier
+      }
     }
     if (kCarryA && 27 % kRing != 0) {
       // the next tile's offsets 0 .. kApf-1 were prefetched into ring
@@ -376,7 +443,7 @@ __device__ __forceinline__ void m2l_mixed_run(LdsMix<P, ADJ> &sm, const float2 *
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int d = gq[t2][e];
-            const float2 z = sm.gb[d < 0 ? kMRegBoxes : d + 2 * kMReg * 2 * nt];
+            const float2 z = sm.gb[buf][d < 0 ? kMRegBoxes : d + 2 * kMReg * 2 * (NT * H + nt)];
             w[2 * e] = z.x;
             w[2 * e + 1] = z.y;
             sgr[nt] += z.x;
@@ -387,11 +454,10 @@ __device__ __forceinline__ void m2l_mixed_run(LdsMix<P, ADJ> &sm, const float2 *
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-          for (int t2 = 0; t2 < 2; ++t2) {
-            acc[mt][nt] = mfma16<PREC>(ga[0][mt][t2], ghi[t2], acc[mt][nt]);
-            acc[mt][nt] = mfma16<PREC>(ga[0][mt][t2], glo[t2], acc[mt][nt]);
-            acc[mt][nt] = mfma16<PREC>(ga[1][mt][t2], ghi[t2], acc[mt][nt]);
-          }
+          for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+            for (int part = 0; part < 3; ++part)
+              acc[mt][nt] = mfma16<PREC>(ga[part == 2][mt][t2], part == 1 ? glo[t2] : ghi[t2], acc[mt][nt]);
         sgr[nt] += __shfl_xor(sgr[nt], 16);
         sgi[nt] += __shfl_xor(sgi[nt], 16);
         sgr[nt] += __shfl_xor(sgr[nt], 32);
@@ -403,7 +469,7 @@ __device__ __forceinline__ void m2l_mixed_run(LdsMix<P, ADJ> &sm, const float2 *
     const float logh = -float(geo.level) * ln2;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      const int gx = geo.X0 + 2 * (j & 7) + CX, gy = geo.Y0 + 2 * (2 * nt + (j >> 3)) + CY;
+      const int gx = geo.X0 + 2 * (j & 7) + CX, gy = geo.Y0 + 2 * (2 * (NT * H + nt) + (j >> 3)) + CY;
       if (gx >= geo.nside || gy >= geo.nside) continue;
       const int64_t box = geo.off + morton2(uint32_t(gx), uint32_t(gy));
 #pragma unroll
@@ -429,41 +495,68 @@ __device__ __forceinline__ void m2l_mixed_run(LdsMix<P, ADJ> &sm, const float2 *
         }
       }
     }
+    __syncthreads();  // end of round r: buffer r & 1 is free, the next tile is staged
   }
 }
 
 template <int P, int PREC, bool ADJ>
-__global__ __launch_bounds__(256, 2) void m2l_mixed_kernel(const float2 *__restrict__ X,
-                                                           const float2 *__restrict__ gbin, float2 *__restrict__ Y,
-                                                           float2 *__restrict__ bout,
-                                                           const unsigned char *__restrict__ bank, TileMap map,
-                                                           int ntiles) {
+__global__ __launch_bounds__(MixK<P>::kThreads, 1) void m2l_mixed_kernel(const float2 *__restrict__ X,
+                                                                         const float2 *__restrict__ gbin,
+                                                                         float2 *__restrict__ Y,
+                                                                         float2 *__restrict__ bout,
+                                                                         const unsigned char *__restrict__ bank,
+                                                                         TileMap map, int ntiles) {
+  using K = MixK<P>;
   __shared__ __attribute__((aligned(16))) LdsMix<P, ADJ> sm;
   const int tid = threadIdx.x;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: the class lives in SGPRs
-  if (ADJ && tid == 0) sm.gb[kMRegBoxes] = make_float2(0.f, 0.f);
-  // every branch runs the same tile loop, hence the same barriers
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: the role lives in SGPRs
+  if (ADJ && tid == 0) {
+    sm.gb[0][kMRegBoxes] = make_float2(0.f, 0.f);
+    sm.gb[1][kMRegBoxes] = make_float2(0.f, 0.f);
+  }
+  // Both roles run the same number of workgroup barriers: per round one at
+  // its end, and with FP16x3 one more in its middle (and in the prologue).
+  if (wave >= K::kCompute) {
+    const int ltid = tid - 64 * K::kCompute;
+    const int G = int(gridDim.x), b = int(blockIdx.x);
+    const int t0 = round_tile(0, b, G);
+    mixed_stage<P, PREC, ADJ>(sm, 0, t0 < ntiles, mgeo(map, t0 < ntiles ? t0 : 0), X, gbin, ltid);
+    __syncthreads();  // tile 0 is staged
+    mixed_loader<P, PREC, ADJ>(sm, X, gbin, map, ntiles, ltid);
+    return;
+  }
+  // compute wave w: class w mod 4, N tiles of half w / 4
   switch (wave) {
-    case 0: m2l_mixed_run<P, PREC, ADJ, 0, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
-    case 1: m2l_mixed_run<P, PREC, ADJ, 1, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
-    case 2: m2l_mixed_run<P, PREC, ADJ, 0, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
-    default: m2l_mixed_run<P, PREC, ADJ, 1, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+    case 0: mixed_compute<P, PREC, ADJ, 0, 0, 0>(sm, Y, bout, bank, map, ntiles, tid); break;
+    case 1: mixed_compute<P, PREC, ADJ, 1, 0, 0>(sm, Y, bout, bank, map, ntiles, tid); break;
+    case 2: mixed_compute<P, PREC, ADJ, 0, 1, 0>(sm, Y, bout, bank, map, ntiles, tid); break;
+    case 3: mixed_compute<P, PREC, ADJ, 1, 1, 0>(sm, Y, bout, bank, map, ntiles, tid); break;
+    default:
+      if constexpr (K::kHalves == 2) {
+        switch (wave) {
+          case 4: mixed_compute<P, PREC, ADJ, 0, 0, 1>(sm, Y, bout, bank, map, ntiles, tid); break;
+          case 5: mixed_compute<P, PREC, ADJ, 1, 0, 1>(sm, Y, bout, bank, map, ntiles, tid); break;
+          case 6: mixed_compute<P, PREC, ADJ, 0, 1, 1>(sm, Y, bout, bank, map, ntiles, tid); break;
+          default: mixed_compute<P, PREC, ADJ, 1, 1, 1>(sm, Y, bout, bank, map, ntiles, tid); break;
+        }
+      }
+      break;
   }
 }
 
 template <int P, int PREC>
 void launch_pp(const float *M, const float *gb_in, float *L, float *b, const TileMap &map, int ntiles, bool adjoint,
                const void *ops, hipStream_t s) {
-  const int slots = 2 * num_cus();
+  const int slots = num_cus();  // one workgroup per compute unit
   const int grid = ntiles < slots ? ntiles : slots;
   const float2 *X = reinterpret_cast<const float2 *>(M);
   float2 *Y = reinterpret_cast<float2 *>(L);
   const unsigned char *bank = static_cast<const unsigned char *>(ops);
   if (adjoint)
-    hipLaunchKernelGGL((m2l_mixed_kernel<P, PREC, true>), dim3(grid), dim3(256), 0, s, X,
+    hipLaunchKernelGGL((m2l_mixed_kernel<P, PREC, true>), dim3(grid), dim3(MixK<P>::kThreads), 0, s, X,
                        reinterpret_cast<const float2 *>(gb_in), Y, nullptr, bank, map, ntiles);
   else
-    hipLaunchKernelGGL((m2l_mixed_kernel<P, PREC, false>), dim3(grid), dim3(256), 0, s, X, nullptr, Y,
+    hipLaunchKernelGGL((m2l_mixed_kernel<P, PREC, false>), dim3(grid), dim3(MixK<P>::kThreads), 0, s, X, nullptr, Y,
                        reinterpret_cast<float2 *>(b), bank, map, ntiles);
 }
 
