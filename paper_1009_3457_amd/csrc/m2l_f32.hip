@@ -285,14 +285,6 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
     // LDS contents change every tile: keep the compiler from caching LDS
     // reads in registers across tiles
     asm volatile("" ::: "memory");
-    // Opaque per tile: stops the per-use sums Ar + Ai from being hoisted out
-    // of the tile loop into extra registers (emits no instructions).
-    if (C::kRegBank) {
-#pragma unroll
-      for (int i = 0; i < NI; ++i)
-#pragma unroll
-        for (int e = 0; e < NA; ++e) asm volatile("" : "+v"(areg[i][e]));
-    }
     const int tn = t + int(gridDim.x);
     const bool has_next = tn < ntiles;
     const TileGeo ngeo = has_next ? tile_geo(map, tn) : geo;
@@ -422,9 +414,9 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
 
     if (WPC == 1) {
       // ---- one wave per class: its accumulators are the whole sum.  The
-      // barrier only orders the LDS buffers (the next tile's block is
-      // complete; this tile's block is no longer read); the output follows.
-      __syncthreads();
+      // output goes out first; the barrier that follows only orders the LDS
+      // buffers (the next tile's block is complete; this tile's block is no
+      // longer read).
       float sgr = 0.f, sgi = 0.f;  // adjoint: sum of gb over the list, for n = 0
       if (ADJ) {
         if (kGbSumLanes) {
@@ -463,6 +455,7 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
           }
         }
       }
+      __syncthreads();
     } else {
       // ---- two waves per class: both publish their partial sums; then each
       // writes half of the output rows (accumulator registers 2h, 2h + 1 of
@@ -538,6 +531,16 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
       }
     }
     if (!has_next) break;
+    // Opaque per tile: stops the per-use sums Ar + Ai from being hoisted out
+    // of the tile loop into extra registers (emits no instructions).  It sits
+    // at the end of the tile, where the operators are in use anyway, so the
+    // first tile still waits for each operator only at its first use.
+    if (C::kRegBank) {
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int e = 0; e < NA; ++e) asm volatile("" : "+v"(areg[i][e]));
+    }
     cur ^= 1;
     t = tn;
     geo = ngeo;
