@@ -221,6 +221,57 @@ def mixed_comparison(seed, dev, steps, warmup, main=None):
     return out
 
 
+def fmm_stage_times(name, prec_name, seed, dev, reps=5):
+    """Per-stage times (ms, median of `reps`) of the whole FMM with every point
+    as both source and target: tree build (with the sorted gathers), P2M, M2M,
+    M2L, L2L, L2P, P2P.  HIP events on the stream; the tree build synchronises
+    with the host (it checks the domain), so it is timed with host clocks."""
+    import torch
+
+    import paper_1009_3457_amd as P
+    from paper_1009_3457_amd import _binding as B
+    import synthetic as sy
+    n, depth, p, kind, _, _ = WORKLOADS[name]
+    prec = B.PRECISIONS[prec_name]
+    xy = torch.from_numpy(_points(kind, n, seed)).to(dev)
+    q = torch.from_numpy(sy.charges(n, seed + 1)).to(dev)
+    P.m2l_operators(p, prec, dev)
+    stream = torch.cuda.current_stream(dev)
+    rows = []
+    for _ in range(reps + 1):
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        perm, ls = P.build_tree(xy, depth)
+        xs, qs = P.gather(xy, perm), P.gather(q, perm)
+        torch.cuda.synchronize(dev)
+        t_tree = (time.perf_counter() - t0) * 1e3
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+        ev[0].record(stream)
+        M = B.p2m(xs, qs, ls, depth, p)
+        ev[1].record(stream)
+        B.m2m(M, depth, p)
+        ev[2].record(stream)
+        Lm, bm = B.m2l(M, depth, p, 2, depth, prec)
+        ev[3].record(stream)
+        L, b = B.l2l(Lm, bm, depth, p)
+        ev[4].record(stream)
+        phi, field = B.l2p(xs, ls, L, b, depth, p)
+        ev[5].record(stream)
+        B.p2p(xs, qs, ls, xs, ls, depth, phi, field)
+        ev[6].record(stream)
+        torch.cuda.synchronize(dev)
+        st = [ev[i].elapsed_time(ev[i + 1]) for i in range(6)]
+        rows.append([t_tree] + st)
+    rows = sorted(rows[1:], key=lambda r: sum(r))  # drop the first (warm-up) pass
+    med = rows[len(rows) // 2]
+    names = ["tree_build_and_gather", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p"]
+    out = {k: v for k, v in zip(names, med)}
+    out["total"] = sum(med)
+    out["workload"] = name
+    out["precision"] = prec_name
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +281,8 @@ def main():
     ap.add_argument("--precision", default=None, choices=["f32", "bf16x3", "f16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision comparison")
+    ap.add_argument("--fmm", action="store_true",
+                    help="also time every stage of the whole FMM (all points as sources and targets)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy, 4 times (reference for "
@@ -291,6 +344,8 @@ def main():
     if default_run and not args.no_mixed:
         out["mixed_vs_f32"] = mixed_comparison(args.seed, dev, max(args.steps // 2, 10),
                                                max(args.warmup // 2, 2), main=w)
+    if args.fmm:
+        out["fmm_stages_ms"] = fmm_stage_times(args.workload, prec_name, args.seed, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w.M.cpu().numpy(), w.depth, w.p)
     print(json.dumps(out))

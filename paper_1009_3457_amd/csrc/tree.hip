@@ -2,10 +2,10 @@
 // of the points by leaf Morton key, plus gather/scatter of per-point rows.
 //
 // The sort is a least-significant-digit radix sort over 4-bit digits of the
-// 2*depth-bit key.  Each pass is three kernels: per-chunk digit counts, one
-// exclusive scan over (digit, chunk), and a scatter in which every item's rank
-// among equal digits of its chunk comes from wave ballots, so each pass is
-// stable and the whole result is deterministic.
+// 2*depth-bit key.  Each pass is: per-chunk digit counts, an exclusive scan
+// over (digit, chunk) (three short kernels), and a scatter in which every
+// item's rank among equal digits of its chunk comes from wave ballots, so
+// each pass is stable and the whole result is deterministic.
 #include "fmm2d_internal.h"
 
 namespace fmm2d {
@@ -17,12 +17,19 @@ constexpr int kDigits = 16;
 
 static inline int64_t nchunks_of(int64_t n) { return (n + kChunk - 1) / kChunk; }
 
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 16;                         // values per thread
+constexpr int kScanBlock = kScanThreads * kScanPer;  // 4096 values per block
+
+static inline int64_t scan_blocks(int64_t m) { return (m + kScanBlock - 1) / kScanBlock; }
+
 static inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 struct TreeWs {
   uint32_t *keys[2];
   int32_t *vals[2];
   uint32_t *count;  // [kDigits][nchunks]
+  uint32_t *part;   // [scan_blocks(kDigits * nchunks)]
   uint32_t *flag;
 };
 
@@ -35,6 +42,7 @@ static TreeWs carve(void *ws, int64_t n) {
   w.vals[0] = reinterpret_cast<int32_t *>(p); p += kb;
   w.vals[1] = reinterpret_cast<int32_t *>(p); p += kb;
   w.count = reinterpret_cast<uint32_t *>(p); p += align256(size_t(kDigits) * nchunks_of(n) * 4);
+  w.part = reinterpret_cast<uint32_t *>(p); p += align256(size_t(scan_blocks(int64_t(kDigits) * nchunks_of(n))) * 4);
   w.flag = reinterpret_cast<uint32_t *>(p);
   return w;
 }
@@ -42,7 +50,8 @@ static TreeWs carve(void *ws, int64_t n) {
 size_t build_tree_ws_bytes(int64_t n, int depth) {
   (void)depth;
   const size_t kb = align256(size_t(n) * 4);
-  return 4 * kb + align256(size_t(kDigits) * nchunks_of(n) * 4) + 256;
+  return 4 * kb + align256(size_t(kDigits) * nchunks_of(n) * 4) +
+         align256(size_t(scan_blocks(int64_t(kDigits) * nchunks_of(n))) * 4) + 256;
 }
 
 // Leaf key of every point; flags points outside [0,1]^2 (NaN included).
@@ -76,27 +85,81 @@ __global__ __launch_bounds__(kSortThreads) void digit_count_kernel(const uint32_
   if (threadIdx.x < kDigits) count[threadIdx.x * nchunks + blockIdx.x] = hist[threadIdx.x];
 }
 
-// In-place exclusive scan of m values by one workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void exclusive_scan_kernel(uint32_t *__restrict__ a, int64_t m) {
-  __shared__ uint32_t part[1024];
-  const int t = threadIdx.x;
-  const int64_t per = (m + 1023) / 1024;
-  const int64_t b = t * per, e = min(m, b + per);
+// In-place exclusive scan of m values (the (digit, chunk) counts), in three
+// coalesced passes: per-block totals of 4096 values, a scan of those totals by
+// one workgroup, and a per-block scan that adds its block's offset.
+
+__device__ inline void load16(const uint32_t *__restrict__ a, int64_t m, int64_t i0, uint32_t (&v)[kScanPer]) {
+#pragma unroll
+  for (int e = 0; e < kScanPer; ++e) v[e] = (i0 + e < m) ? a[i0 + e] : 0u;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t *__restrict__ a, int64_t m,
+                                                                   uint32_t *__restrict__ part) {
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  uint32_t v[kScanPer];
+  load16(a, m, blockIdx.x * int64_t(kScanBlock) + threadIdx.x * int64_t(kScanPer), v);
   uint32_t s = 0;
-  for (int64_t i = b; i < e; ++i) s += a[i];
-  part[t] = s;
+#pragma unroll
+  for (int e = 0; e < kScanPer; ++e) s += v[e];
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
   __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {  // Hillis-Steele inclusive scan of the partials
-    uint32_t v = (t >= d) ? part[t - d] : 0u;
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / 64; ++w) t += wsum[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+// exclusive scan of the nb block totals by one workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void scan_partials_kernel(uint32_t *__restrict__ part, int64_t nb) {
+  __shared__ uint32_t buf[1024];
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < nb; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const uint32_t v = i < nb ? part[i] : 0u;
+    buf[threadIdx.x] = v;
     __syncthreads();
-    part[t] += v;
+    for (int d = 1; d < 1024; d <<= 1) {  // Hillis-Steele inclusive scan
+      const uint32_t u = (int(threadIdx.x) >= d) ? buf[threadIdx.x - d] : 0u;
+      __syncthreads();
+      buf[threadIdx.x] += u;
+      __syncthreads();
+    }
+    if (i < nb) part[i] = carry + buf[threadIdx.x] - v;
+    carry += buf[1023];
     __syncthreads();
   }
-  uint32_t run = (t > 0) ? part[t - 1] : 0u;
-  for (int64_t i = b; i < e; ++i) {
-    const uint32_t v = a[i];
-    a[i] = run;
-    run += v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(uint32_t *__restrict__ a, int64_t m,
+                                                                  const uint32_t *__restrict__ part) {
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  const int64_t i0 = blockIdx.x * int64_t(kScanBlock) + threadIdx.x * int64_t(kScanPer);
+  uint32_t v[kScanPer];
+  load16(a, m, i0, v);
+  uint32_t s = 0;
+#pragma unroll
+  for (int e = 0; e < kScanPer; ++e) s += v[e];
+  // exclusive scan of the thread sums within the wave
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t inc = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t u = __shfl_up(inc, d);
+    if (lane >= d) inc += u;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t off = part[blockIdx.x] + inc - s;
+  for (int w = 0; w < wave; ++w) off += wsum[w];
+#pragma unroll
+  for (int e = 0; e < kScanPer; ++e) {
+    if (i0 + e < m) a[i0 + e] = off;
+    off += v[e];
   }
 }
 
@@ -173,7 +236,10 @@ int launch_build_tree(const float *xy, int64_t n, int depth, int32_t *perm, int3
     for (int shift = 0; shift < bits; shift += 4) {
       hipLaunchKernelGGL(digit_count_kernel, dim3(unsigned(nchunks)), dim3(kSortThreads), 0, s, w.keys[cur], n,
                          shift, nchunks, w.count);
-      hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(1024), 0, s, w.count, int64_t(kDigits) * nchunks);
+      const int64_t m = int64_t(kDigits) * nchunks, nb = scan_blocks(m);
+      hipLaunchKernelGGL(scan_reduce_kernel, dim3(unsigned(nb)), dim3(kScanThreads), 0, s, w.count, m, w.part);
+      hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, s, w.part, nb);
+      hipLaunchKernelGGL(scan_apply_kernel, dim3(unsigned(nb)), dim3(kScanThreads), 0, s, w.count, m, w.part);
       hipLaunchKernelGGL(digit_scatter_kernel, dim3(unsigned(nchunks)), dim3(kSortThreads), 0, s, w.keys[cur],
                          w.vals[cur], w.keys[cur ^ 1], w.vals[cur ^ 1], n, shift, nchunks, w.count);
       cur ^= 1;
