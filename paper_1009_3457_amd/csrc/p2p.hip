@@ -1,6 +1,7 @@
 // Near field (Sec. 2.1, stage 5): direct interactions with the 3x3 block of
-// leaves around each target's leaf, and the transpose for gradients.  One
-// thread per target (per source for the transpose), FP32 arithmetic.
+// leaves around each target's leaf, and the transpose for gradients, in FP32
+// arithmetic.  The forward pass runs one wave per target leaf (below); the
+// transpose runs one thread per source.
 #include "fmm2d_internal.h"
 
 namespace fmm2d {
@@ -15,46 +16,109 @@ __device__ inline int64_t leaf_of_p2p(const int32_t *__restrict__ ls, int64_t nl
   return lo;
 }
 
-__global__ void p2p_kernel(const float2 *__restrict__ xy, const float *__restrict__ q, const int32_t *__restrict__ ls,
-                           const float2 *__restrict__ txy, const int32_t *__restrict__ tls, int64_t nt, int depth,
-                           float2 *__restrict__ phi, float2 *__restrict__ field) {
-  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+// atan2(y, x) for (x, y) != (0, 0): octant reduction to a = min/max in
+// [0, 1] and atan(a) = a P(a^2), P an odd degree-15 polynomial fitted here to
+// atan on [0, 1] (weighted least squares driven towards equal ripple; largest
+// error 1.0e-7 when evaluated in FP32).  Principal branch, (-pi, pi].
+__device__ inline float atan2_p2p(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+  const float a = mn * __builtin_amdgcn_rcpf(mx);
+  const float t = a * a;
+  float r = -0.00405455008f;
+  r = fmaf(r, t, 0.0218629036f);
+  r = fmaf(r, t, -0.0559122637f);
+  r = fmaf(r, t, 0.0964219347f);
+  r = fmaf(r, t, -0.139086291f);
+  r = fmaf(r, t, 0.199465662f);
+  r = fmaf(r, t, -0.333298594f);
+  r = fmaf(r, t, 0.999999344f);
+  r *= a;
+  if (ay > ax) r = 1.57079632679f - r;
+  if (x < 0.f) r = 3.14159265359f - r;
+  return copysignf(r, y);
+}
+
+// One wave per target leaf.  The wave's lanes are split into NTG targets x
+// NPH source phases (NTG the leaf's target count rounded up to a power of
+// two, at most 64): lane (i, ph) sums sources ph, ph + NPH, ... of each of
+// the 3x3 neighbour leaves for target i, and the phases are then combined
+// by lane shuffles in a fixed order.  All lanes read the same few sources at
+// a time, so source loads are served once per wave.
+template <bool PHI, bool FIELD>
+__global__ __launch_bounds__(256) void p2p_kernel(const float2 *__restrict__ xy, const float *__restrict__ q,
+                                                  const int32_t *__restrict__ ls, const float2 *__restrict__ txy,
+                                                  const int32_t *__restrict__ tls, int depth,
+                                                  float2 *__restrict__ phi, float2 *__restrict__ field) {
   const int64_t nleaf = int64_t(1) << (2 * depth);
-  if (t >= nt || t >= int64_t(tls[nleaf])) return;
-  const int64_t m = leaf_of_p2p(tls, nleaf, t);
+  const int64_t leaf = blockIdx.x * int64_t(4) + (threadIdx.x >> 6);
+  if (leaf >= nleaf) return;
+  const int lane = threadIdx.x & 63;
+  const int32_t t0 = tls[leaf], nt = tls[leaf + 1] - t0;
+  if (nt <= 0) return;
   uint32_t ix, iy;
-  unmorton2(uint32_t(m), ix, iy);
+  unmorton2(uint32_t(leaf), ix, iy);
   const int side = 1 << depth;
-  const float2 z = txy[t];
-  float pr = 0.f, pi = 0.f, fr = 0.f, fi = 0.f;
-  for (int dy = -1; dy <= 1; ++dy) {
-    const int sy = int(iy) + dy;
-    if (sy < 0 || sy >= side) continue;
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int sx = int(ix) + dx;
-      if (sx < 0 || sx >= side) continue;
-      const uint32_t sm = morton2(uint32_t(sx), uint32_t(sy));
-      for (int32_t s = ls[sm]; s < ls[sm + 1]; ++s) {
+  int32_t sb[9], se[9];  // source ranges of the 3x3 neighbourhood (empty outside the grid)
+#pragma unroll
+  for (int d = 0; d < 9; ++d) {
+    const int sx = int(ix) + d % 3 - 1, sy = int(iy) + d / 3 - 1;
+    const bool in = sx >= 0 && sy >= 0 && sx < side && sy < side;
+    const uint32_t sm = in ? morton2(uint32_t(sx), uint32_t(sy)) : 0u;
+    sb[d] = in ? ls[sm] : 0;
+    se[d] = in ? ls[sm + 1] : 0;
+  }
+  int ntg = 1;
+  while (ntg < nt && ntg < 64) ntg <<= 1;
+  const int nph = 64 / ntg;
+  const int ti = lane & (ntg - 1), ph = lane / ntg;
+  constexpr float kHalfLn2 = 0.346573590279972654709f;  // log(r2) / 2 = kHalfLn2 log2(r2)
+  for (int32_t c0 = 0; c0 < nt; c0 += ntg) {
+    const int32_t t = t0 + c0 + ti;
+    const bool act = c0 + ti < nt;
+    const float2 z = txy[act ? t : t0];
+    float pr = 0.f, pi = 0.f, fr = 0.f, fi = 0.f;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) {
+      for (int32_t s = sb[d] + ph; s < se[d]; s += nph) {
         const float2 zs = xy[s];
+        const float qs0 = q[s];
         const float rx = z.x - zs.x, ry = z.y - zs.y;
-        const float r2 = rx * rx + ry * ry;
-        if (r2 == 0.f) continue;  // coincident pair
-        const float qs = q[s];
-        pr += qs * 0.5f * logf(r2);
-        pi += qs * atan2f(ry, rx);
-        const float inv = qs / r2;
-        fr += inv * rx;
-        fi -= inv * ry;
+        const float r2 = fmaf(rx, rx, ry * ry);
+        const bool self = r2 == 0.f;  // coincident pair: skipped
+        const float qs = self ? 0.f : qs0;
+        const float r2s = self ? 1.f : r2;
+        if (PHI) {
+          pr = fmaf(qs, __builtin_amdgcn_logf(r2s), pr);  // hardware log2
+          pi = fmaf(qs, atan2_p2p(ry, self ? 1.f : rx), pi);
+        }
+        if (FIELD) {
+          const float inv = qs * __builtin_amdgcn_rcpf(r2s);  // hardware reciprocal (1 ulp)
+          fr = fmaf(inv, rx, fr);
+          fi = fmaf(-inv, ry, fi);
+        }
       }
     }
-  }
-  if (phi) {
-    const float2 o = phi[t];
-    phi[t] = make_float2(o.x + pr, o.y + pi);
-  }
-  if (field) {
-    const float2 o = field[t];
-    field[t] = make_float2(o.x + fr, o.y + fi);
+    for (int m = ntg; m < 64; m <<= 1) {  // combine the phases: lane ph = 0 ends with the total
+      if (PHI) {
+        pr += __shfl_xor(pr, m);
+        pi += __shfl_xor(pi, m);
+      }
+      if (FIELD) {
+        fr += __shfl_xor(fr, m);
+        fi += __shfl_xor(fi, m);
+      }
+    }
+    if (act && ph == 0) {
+      if (PHI) {
+        const float2 o = phi[t];
+        phi[t] = make_float2(o.x + kHalfLn2 * pr, o.y + pi);
+      }
+      if (FIELD) {
+        const float2 o = field[t];
+        field[t] = make_float2(o.x + fr, o.y + fi);
+      }
+    }
   }
 }
 
@@ -110,10 +174,16 @@ __global__ void p2p_backward_kernel(const float2 *__restrict__ xy, const float *
 
 int launch_p2p(const float *xy, const float *q, const int32_t *ls, const float *txy, const int32_t *tls,
                  int64_t nt, int depth, float *phi, float *field, hipStream_t s) {
-  if (nt == 0) return FMM2D_OK;
-  hipLaunchKernelGGL(p2p_kernel, dim3(unsigned((nt + 255) / 256)), dim3(256), 0, s,
-                     reinterpret_cast<const float2 *>(xy), q, ls, reinterpret_cast<const float2 *>(txy), tls, nt,
-                     depth, reinterpret_cast<float2 *>(phi), reinterpret_cast<float2 *>(field));
+  if (nt == 0 || (!phi && !field)) return FMM2D_OK;
+  const int64_t nleaf = int64_t(1) << (2 * depth);
+  const dim3 grid(unsigned((nleaf + 3) / 4)), block(256);
+  auto X = reinterpret_cast<const float2 *>(xy);
+  auto T = reinterpret_cast<const float2 *>(txy);
+  auto Ph = reinterpret_cast<float2 *>(phi);
+  auto F = reinterpret_cast<float2 *>(field);
+  if (phi && field) hipLaunchKernelGGL((p2p_kernel<true, true>), grid, block, 0, s, X, q, ls, T, tls, depth, Ph, F);
+  else if (phi) hipLaunchKernelGGL((p2p_kernel<true, false>), grid, block, 0, s, X, q, ls, T, tls, depth, Ph, F);
+  else hipLaunchKernelGGL((p2p_kernel<false, true>), grid, block, 0, s, X, q, ls, T, tls, depth, Ph, F);
   return check_launch("p2p");
 }
 
