@@ -224,8 +224,10 @@ def mixed_comparison(seed, dev, steps, warmup, main=None):
 def fmm_stage_times(name, prec_name, seed, dev, reps=5):
     """Per-stage times (ms, median of `reps`) of the whole FMM with every point
     as both source and target: tree build (with the sorted gathers), P2M, M2M,
-    M2L, L2L, L2P, P2P.  HIP events on the stream; the tree build synchronises
-    with the host (it checks the domain), so it is timed with host clocks."""
+    M2L, L2L, L2P, P2P, then the reverse pass for seeded cotangents of (phi,
+    field): L2P^T, L2L^T, M2L^T, M2M^T, P2M^T, P2P^T.  HIP events on the
+    stream; the tree build synchronises with the host (it checks the domain),
+    so it is timed with host clocks."""
     import torch
 
     import paper_1009_3457_amd as P
@@ -237,6 +239,8 @@ def fmm_stage_times(name, prec_name, seed, dev, reps=5):
     q = torch.from_numpy(sy.charges(n, seed + 1)).to(dev)
     P.m2l_operators(p, prec, dev)
     stream = torch.cuda.current_stream(dev)
+    gen = torch.Generator().manual_seed(seed + 2)
+    cot = torch.randn(2, n, dtype=torch.complex64, generator=gen).to(dev)
     rows = []
     for _ in range(reps + 1):
         torch.cuda.synchronize(dev)
@@ -245,7 +249,7 @@ def fmm_stage_times(name, prec_name, seed, dev, reps=5):
         xs, qs = P.gather(xy, perm), P.gather(q, perm)
         torch.cuda.synchronize(dev)
         t_tree = (time.perf_counter() - t0) * 1e3
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(13)]
         ev[0].record(stream)
         M = B.p2m(xs, qs, ls, depth, p)
         ev[1].record(stream)
@@ -259,14 +263,29 @@ def fmm_stage_times(name, prec_name, seed, dev, reps=5):
         ev[5].record(stream)
         B.p2p(xs, qs, ls, xs, ls, depth, phi, field)
         ev[6].record(stream)
+        cphi, cfield = cot[0], cot[1]
+        gL, gb = B.l2p_backward(xs, ls, cphi, cfield, depth, p)
+        ev[7].record(stream)
+        gLm, gbm = B.l2l_backward(gL, gb, depth, p)
+        ev[8].record(stream)
+        gM = B.m2l_backward(gLm, gbm, depth, p, 2, depth, prec)
+        ev[9].record(stream)
+        B.m2m_backward(gM, depth, p)
+        ev[10].record(stream)
+        gq, G = B.p2m_backward(xs, qs, ls, depth, p, gM)
+        ev[11].record(stream)
+        B.p2p_backward(xs, qs, ls, xs, ls, depth, cphi, cfield, gq, G)
+        ev[12].record(stream)
         torch.cuda.synchronize(dev)
-        st = [ev[i].elapsed_time(ev[i + 1]) for i in range(6)]
+        st = [ev[i].elapsed_time(ev[i + 1]) for i in range(12)]
         rows.append([t_tree] + st)
     rows = sorted(rows[1:], key=lambda r: sum(r))  # drop the first (warm-up) pass
     med = rows[len(rows) // 2]
-    names = ["tree_build_and_gather", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p"]
+    names = ["tree_build_and_gather", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p",
+             "l2p_T", "l2l_T", "m2l_T", "m2m_T", "p2m_T", "p2p_T"]
     out = {k: v for k, v in zip(names, med)}
-    out["total"] = sum(med)
+    out["forward_total"] = sum(med[:7])
+    out["backward_total"] = sum(med[7:])
     out["workload"] = name
     out["precision"] = prec_name
     return out

@@ -1,9 +1,11 @@
 // Upward sweep (P2M, M2M), L2L and L2P (Sec. 2.1, stages 2-4) in the scaled
 // basis of fmm2d.h, and the plain transposes of each for gradients.
 //
-// These stages are O(N p) or O(boxes p^2) and not the hot path; they are
-// written plainly: one thread per (box, order) or per point.  L2L and L2P
-// run in FP64 (the deep-level accumulation of local expansions).
+// These stages are O(N p) or O(boxes p^2) and not the hot path: one thread
+// per box or per point.  M2M and L2L shift coefficient vectors held in
+// registers by repeated Horner steps; L2P finds a target's leaf from its
+// coordinates.  L2L and L2P run in FP64 (the
+// deep-level accumulation of local expansions).
 #include "fmm2d_internal.h"
 
 namespace fmm2d {
@@ -19,6 +21,19 @@ __device__ inline int64_t leaf_of(const int32_t *__restrict__ ls, int64_t nleaf,
   return lo;
 }
 
+// Leaf of sorted target t at `z`: the leaf the tree build assigns to z
+// (floor of z 2^depth, clamped), confirmed against the leaf ranges; a search
+// of the ranges when they disagree.
+__device__ inline int64_t leaf_of_point(float2 z, const int32_t *__restrict__ ls, int64_t nleaf, int depth,
+                                        int64_t t) {
+  const float side = float(1 << depth);  // z 2^depth is exact in FP32
+  const int lim = (1 << depth) - 1;
+  const int ix = min(max(int(floorf(z.x * side)), 0), lim), iy = min(max(int(floorf(z.y * side)), 0), lim);
+  const int64_t m = morton2(uint32_t(ix), uint32_t(iy));
+  if (int64_t(ls[m]) <= t && t < int64_t(ls[m + 1])) return m;
+  return leaf_of(ls, nleaf, t);
+}
+
 // (x - c)/h for a point and the centre of leaf m at level `depth`.
 __device__ inline float2 scaled_offset(float2 p, uint32_t m, int depth) {
   uint32_t ix, iy;
@@ -26,12 +41,6 @@ __device__ inline float2 scaled_offset(float2 p, uint32_t m, int depth) {
   const float h = ldexpf(1.f, -depth);
   const float cx = (float(ix) + 0.5f) * h, cy = (float(iy) + 0.5f) * h;
   return make_float2((p.x - cx) * float(1 << depth), (p.y - cy) * float(1 << depth));
-}
-
-// u = (c_child - c_parent)/h_child = ((2 cx - 1) + i (2 cy - 1))/2 for child class (cx, cy).
-__host__ __device__ inline void child_u(int cx, int cy, double &ur, double &ui) {
-  ur = cx ? 0.5 : -0.5;
-  ui = cy ? 0.5 : -0.5;
 }
 
 // ------------------------------------------------------------------ P2M --
@@ -95,183 +104,219 @@ __global__ void p2m_backward_kernel(const float2 *__restrict__ xy, const float *
   G[i] = make_float2(sc * dr, sc * di);
 }
 
-// ------------------------------------------------------------------ M2M --
-// M~_k(parent) = 2^-k sum_children sum_{j<=k} C(k,j) u^(k-j) M~_j(child).
-// Every coefficient of this map (binomials <= C(19,9), powers of (+-1+-i)/2)
-// is exact in FP32.
+// ------------------------------------------------------- shifts by u --
+// A shift between a box and its parent applies the binomial matrix of the
+// offset u = (+-1 +- i)/2 (child centre minus parent centre, in child
+// widths) to a coefficient vector held in registers, by repeated Horner
+// steps: p(p-1)/2 complex multiply-adds, no binomial or power tables.
 
-__global__ void m2m_kernel(float2 *__restrict__ M, int lpar, int p) {
-  const int64_t npar = int64_t(1) << (2 * lpar);
-  const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (e >= npar * p) return;
-  const int64_t P_ = e / p;
-  const int k = int(e - P_ * p);
-  uint32_t px, py;
-  unmorton2(uint32_t(P_), px, py);
-  float accr = 0.f, acci = 0.f;
-  for (int c = 0; c < 4; ++c) {
-    const int cx = c & 1, cy = c >> 1;
-    const uint32_t ch = morton2(2 * px + cx, 2 * py + cy);
-    const float2 *Mc = M + (level_off(lpar + 1) + ch) * p;
-    const float ur = cx ? 0.5f : -0.5f, ui = cy ? 0.5f : -0.5f;
-    float binom = 1.f, wr = 1.f, wi = 0.f;  // C(k, j), u^(k-j) for j = k downwards
-    for (int j = k; j >= 0; --j) {
-      const float2 mj = Mc[j];
-      accr += binom * (wr * mj.x - wi * mj.y);
-      acci += binom * (wr * mj.y + wi * mj.x);
-      if (j > 0) {
-        binom = binom * float(j) / float(k - j + 1);
-        const float tr = wr * ur - wi * ui;
-        wi = wr * ui + wi * ur;
-        wr = tr;
-      }
+// a_n <- sum_{m>=n} C(m,n) u^(m-n) a_m  (re-expanding a Taylor series about a point shifted by u)
+template <int P, typename T>
+__device__ inline void shift_down(T (&ar)[P], T (&ai)[P], T ur, T ui) {
+#pragma unroll
+  for (int k = 0; k < P - 1; ++k)
+#pragma unroll
+    for (int j = P - 2; j >= k; --j) {
+      ar[j] += ur * ar[j + 1] - ui * ai[j + 1];
+      ai[j] += ur * ai[j + 1] + ui * ar[j + 1];
     }
-  }
-  const float sc = ldexpf(1.f, -k);
-  M[(level_off(lpar) + P_) * p + k] = make_float2(sc * accr, sc * acci);
 }
 
-// gM~_j(child) += sum_{k>=j} 2^-k C(k,j) u^(k-j) gM~_k(parent).
-__global__ void m2m_backward_kernel(float2 *__restrict__ gM, int lchild, int p) {
+// a_k <- sum_{j<=k} C(k,j) u^(k-j) a_j  (the transpose of shift_down)
+template <int P, typename T>
+__device__ inline void shift_up(T (&ar)[P], T (&ai)[P], T ur, T ui) {
+#pragma unroll
+  for (int k = P - 2; k >= 0; --k)
+#pragma unroll
+    for (int j = k; j <= P - 2; ++j) {
+      ar[j + 1] += ur * ar[j] - ui * ai[j];
+      ai[j + 1] += ur * ai[j] + ui * ar[j];
+    }
+}
+
+// ------------------------------------------------------------------ M2M --
+// M~_k(parent) = 2^-k sum_children sum_{j<=k} C(k,j) u^(k-j) M~_j(child):
+// one thread per parent box.
+
+template <int P>
+__global__ __launch_bounds__(256) void m2m_kernel(float2 *__restrict__ M, int lpar) {
+  const int64_t npar = int64_t(1) << (2 * lpar);
+  const int64_t par = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (par >= npar) return;
+  uint32_t px, py;
+  unmorton2(uint32_t(par), px, py);
+  float sr[P], si[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) sr[k] = si[k] = 0.f;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const uint32_t ch = morton2(2 * px + (c & 1), 2 * py + (c >> 1));
+    const float4 *Mc = reinterpret_cast<const float4 *>(M + (level_off(lpar + 1) + ch) * P);
+    float ar[P], ai[P];
+#pragma unroll
+    for (int j = 0; j < P / 2; ++j) {
+      const float4 v = Mc[j];
+      ar[2 * j] = v.x, ai[2 * j] = v.y, ar[2 * j + 1] = v.z, ai[2 * j + 1] = v.w;
+    }
+    shift_up<P>(ar, ai, (c & 1) ? 0.5f : -0.5f, (c >> 1) ? 0.5f : -0.5f);
+#pragma unroll
+    for (int k = 0; k < P; ++k) sr[k] += ar[k], si[k] += ai[k];
+  }
+  float4 *out = reinterpret_cast<float4 *>(M + (level_off(lpar) + par) * P);
+  float sc = 1.f;  // 2^-k
+#pragma unroll
+  for (int j = 0; j < P / 2; ++j) {
+    const float s0 = sc, s1 = 0.5f * sc;
+    out[j] = make_float4(s0 * sr[2 * j], s0 * si[2 * j], s1 * sr[2 * j + 1], s1 * si[2 * j + 1]);
+    sc *= 0.25f;
+  }
+}
+
+// gM~_j(child) += sum_{k>=j} C(k,j) u^(k-j) 2^-k gM~_k(parent): one thread per child box.
+template <int P>
+__global__ __launch_bounds__(256) void m2m_backward_kernel(float2 *__restrict__ gM, int lchild) {
   const int64_t nch = int64_t(1) << (2 * lchild);
-  const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (e >= nch * p) return;
-  const int64_t c = e / p;
-  const int j = int(e - c * p);
+  const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (c >= nch) return;
   uint32_t ix, iy;
   unmorton2(uint32_t(c), ix, iy);
   const uint32_t par = morton2(ix >> 1, iy >> 1);
-  const float2 *gp = gM + (level_off(lchild - 1) + par) * p;
-  const float ur = (ix & 1) ? 0.5f : -0.5f, ui = (iy & 1) ? 0.5f : -0.5f;
-  float binom = 1.f, wr = 1.f, wi = 0.f;  // C(k, j), u^(k-j) for k = j upwards
-  float accr = 0.f, acci = 0.f;
-  for (int k = j; k < p; ++k) {
-    const float2 g = gp[k];
-    const float sc = ldexpf(binom, -k);
-    accr += sc * (wr * g.x - wi * g.y);
-    acci += sc * (wr * g.y + wi * g.x);
-    binom = binom * float(k + 1) / float(k + 1 - j);
-    const float tr = wr * ur - wi * ui;
-    wi = wr * ui + wi * ur;
-    wr = tr;
+  const float4 *gp = reinterpret_cast<const float4 *>(gM + (level_off(lchild - 1) + par) * P);
+  float ar[P], ai[P];
+  float sc = 1.f;  // 2^-k
+#pragma unroll
+  for (int j = 0; j < P / 2; ++j) {
+    const float4 v = gp[j];
+    ar[2 * j] = sc * v.x, ai[2 * j] = sc * v.y;
+    ar[2 * j + 1] = 0.5f * sc * v.z, ai[2 * j + 1] = 0.5f * sc * v.w;
+    sc *= 0.25f;
   }
-  float2 *dst = gM + (level_off(lchild) + c) * p + j;
-  const float2 old = *dst;
-  *dst = make_float2(old.x + accr, old.y + acci);
+  shift_down<P>(ar, ai, (ix & 1) ? 0.5f : -0.5f, (iy & 1) ? 0.5f : -0.5f);
+  float4 *dst = reinterpret_cast<float4 *>(gM + (level_off(lchild) + c) * P);
+#pragma unroll
+  for (int j = 0; j < P / 2; ++j) {
+    const float4 o = dst[j];
+    dst[j] = make_float4(o.x + ar[2 * j], o.y + ai[2 * j], o.z + ar[2 * j + 1], o.w + ai[2 * j + 1]);
+  }
 }
 
 // ------------------------------------------------------------------ L2L --
 // L~_n(child) = Lm2l_n(child) + sum_{m>=n} C(m,n) u^(m-n) 2^-(m+1) L~_m(parent)
-// b(child)    = bm2l(child) + b(parent) + sum_m L~_m(parent) (u/2)^(m+1)/(m+1)
+// b(child)    = bm2l(child) + b(parent) + sum_m 2^-(m+1) L~_m(parent) u^(m+1)/(m+1)
 
 __global__ void zero_f64_kernel(double *__restrict__ a, int64_t n) {
   const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (i < n) a[i] = 0.0;
 }
 
-__global__ void l2l_kernel(const float2 *__restrict__ Lm2l, const float2 *__restrict__ bm2l, double2 *__restrict__ L,
-                           double2 *__restrict__ b, int l, int p) {
+// One thread per child box at level l.
+template <int P>
+__global__ __launch_bounds__(256) void l2l_kernel(const float2 *__restrict__ Lm2l, const float2 *__restrict__ bm2l,
+                                                  double2 *__restrict__ L, double2 *__restrict__ b, int l) {
   const int64_t nb = int64_t(1) << (2 * l);
-  const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (e >= nb * p) return;
-  const int64_t c = e / p;
-  const int n = int(e - c * p);
+  const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (c >= nb) return;
+  const bool has_parent = l >= 3;  // levels 0-1 carry no local expansion
   uint32_t ix, iy;
   unmorton2(uint32_t(c), ix, iy);
   const int64_t gc = level_off(l) + c;
-  const float2 own = Lm2l[gc * p + n];
-  double accr = own.x, acci = own.y;
-  const bool has_parent = l >= 3;  // levels 0-1 carry no local expansion
-  const uint32_t par = morton2(ix >> 1, iy >> 1);
-  const double2 *Lp = L + (level_off(l - 1) + par) * p;
-  double ur, ui;
-  child_u(ix & 1, iy & 1, ur, ui);
+  const double ur = (ix & 1) ? 0.5 : -0.5, ui = (iy & 1) ? 0.5 : -0.5;
+  double ar[P], ai[P];
+  double br = 0.0, bi = 0.0;
   if (has_parent) {
-    double binom = 1.0, wr = 1.0, wi = 0.0;  // C(m,n), u^(m-n) for m = n upwards
-    for (int m = n; m < p; ++m) {
-      const double2 Lm = Lp[m];
-      const double sc = ldexp(binom, -(m + 1));
-      accr += sc * (wr * Lm.x - wi * Lm.y);
-      acci += sc * (wr * Lm.y + wi * Lm.x);
-      binom = binom * double(m + 1) / double(m + 1 - n);
-      const double tr = wr * ur - wi * ui;
-      wi = wr * ui + wi * ur;
-      wr = tr;
+    const int64_t gp = level_off(l - 1) + morton2(ix >> 1, iy >> 1);
+    const double2 *Lp = L + gp * P;
+    double sc = 0.5;  // 2^-(m+1)
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      const double2 v = Lp[m];
+      ar[m] = sc * v.x, ai[m] = sc * v.y;
+      sc *= 0.5;
     }
-  }
-  L[gc * p + n] = make_double2(accr, acci);
-  if (b && n == 0) {
-    const float2 bo = bm2l[gc];
-    double br = bo.x, bi = bo.y;
-    if (has_parent) {
-      const double2 bp = b[level_off(l - 1) + par];
+    if (b) {
+      // b(parent) + sum_m a_m u^(m+1)/(m+1), Horner in u
+#pragma unroll
+      for (int m = P - 1; m >= 0; --m) {
+        constexpr double one = 1.0;
+        const double inv = one / double(m + 1);
+        const double tr = br + inv * ar[m], ti = bi + inv * ai[m];
+        br = tr * ur - ti * ui;
+        bi = tr * ui + ti * ur;
+      }
+      const double2 bp = b[gp];
       br += bp.x;
       bi += bp.y;
-      const double vr = 0.5 * ur, vi = 0.5 * ui;
-      double wr = vr, wi = vi;  // (u/2)^(m+1)
-      for (int m = 0; m < p; ++m) {
-        const double2 Lm = Lp[m];
-        const double inv = 1.0 / double(m + 1);
-        br += inv * (wr * Lm.x - wi * Lm.y);
-        bi += inv * (wr * Lm.y + wi * Lm.x);
-        const double tr = wr * vr - wi * vi;
-        wi = wr * vi + wi * vr;
-        wr = tr;
-      }
     }
-    b[gc] = make_double2(br, bi);
+    shift_down<P>(ar, ai, ur, ui);
+  } else {
+#pragma unroll
+    for (int m = 0; m < P; ++m) ar[m] = ai[m] = 0.0;
+  }
+  const float4 *own = reinterpret_cast<const float4 *>(Lm2l + gc * P);
+  double2 *out = L + gc * P;
+#pragma unroll
+  for (int j = 0; j < P / 2; ++j) {
+    const float4 o = own[j];
+    out[2 * j] = make_double2(ar[2 * j] + o.x, ai[2 * j] + o.y);
+    out[2 * j + 1] = make_double2(ar[2 * j + 1] + o.z, ai[2 * j + 1] + o.w);
+  }
+  if (b) {
+    const float2 bo = bm2l[gc];
+    b[gc] = make_double2(br + bo.x, bi + bo.y);
   }
 }
 
-// Upward transpose for one parent level lp (children at lp + 1):
-// gL_m(P) = sum_c [ sum_{n<=m} C(m,n) u^(m-n) 2^-(m+1) gL_n(c) + gb(c) (u/2)^(m+1)/(m+1) ],
-// gb(P) = sum_c gb(c).
-__global__ void l2l_backward_kernel(double2 *__restrict__ gL, double2 *__restrict__ gb, int lp, int p) {
+// L2L^T, one thread per parent box at level lp:
+//   gL~_m(parent) = 2^-(m+1) sum_children [sum_{n<=m} C(m,n) u^(m-n) gL~_n(child) + gb(child) u^(m+1)/(m+1)]
+//   gb(parent)    = sum_children gb(child)
+template <int P>
+__global__ __launch_bounds__(256) void l2l_backward_kernel(double2 *__restrict__ gL, double2 *__restrict__ gb, int lp) {
   const int64_t npar = int64_t(1) << (2 * lp);
-  const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (e >= npar * p) return;
-  const int64_t P_ = e / p;
-  const int m = int(e - P_ * p);
+  const int64_t par = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (par >= npar) return;
   uint32_t px, py;
-  unmorton2(uint32_t(P_), px, py);
-  double accr = 0.0, acci = 0.0, gbr = 0.0, gbi = 0.0;
+  unmorton2(uint32_t(par), px, py);
+  double sr[P], si[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) sr[m] = si[m] = 0.0;
+  double gbr = 0.0, gbi = 0.0;
+#pragma unroll 1
   for (int c = 0; c < 4; ++c) {
-    const int cx = c & 1, cy = c >> 1;
-    const uint32_t ch = morton2(2 * px + cx, 2 * py + cy);
-    const double2 *gc = gL + (level_off(lp + 1) + ch) * p;
-    double ur, ui;
-    child_u(cx, cy, ur, ui);
-    double binom = 1.0, wr = 1.0, wi = 0.0;  // C(m,n), u^(m-n) for n = m downwards
-    for (int n = m; n >= 0; --n) {
-      const double2 g = gc[n];
-      const double sc = ldexp(binom, -(m + 1));
-      accr += sc * (wr * g.x - wi * g.y);
-      acci += sc * (wr * g.y + wi * g.x);
-      if (n > 0) {
-        binom = binom * double(n) / double(m - n + 1);
+    const int64_t ch = level_off(lp + 1) + morton2(2 * px + (c & 1), 2 * py + (c >> 1));
+    const double ur = (c & 1) ? 0.5 : -0.5, ui = (c >> 1) ? 0.5 : -0.5;
+    const double2 *gc = gL + ch * P;
+    double ar[P], ai[P];
+#pragma unroll
+    for (int n = 0; n < P; ++n) {
+      const double2 v = gc[n];
+      ar[n] = v.x, ai[n] = v.y;
+    }
+    shift_up<P>(ar, ai, ur, ui);
+#pragma unroll
+    for (int m = 0; m < P; ++m) sr[m] += ar[m], si[m] += ai[m];
+    if (gb) {
+      const double2 g = gb[ch];
+      double wr = ur * g.x - ui * g.y, wi = ur * g.y + ui * g.x;  // gb u^(m+1)
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        constexpr double one = 1.0;
+        const double inv = one / double(m + 1);
+        sr[m] += inv * wr, si[m] += inv * wi;
         const double tr = wr * ur - wi * ui;
         wi = wr * ui + wi * ur;
         wr = tr;
       }
-    }
-    if (gb) {
-      const double2 g = gb[level_off(lp + 1) + ch];
-      const double vr = 0.5 * ur, vi = 0.5 * ui;
-      double wr2 = vr, wi2 = vi;
-      for (int k = 0; k < m; ++k) {
-        const double tr = wr2 * vr - wi2 * vi;
-        wi2 = wr2 * vi + wi2 * vr;
-        wr2 = tr;
-      }
-      const double inv = 1.0 / double(m + 1);
-      accr += inv * (wr2 * g.x - wi2 * g.y);
-      acci += inv * (wr2 * g.y + wi2 * g.x);
-      gbr += g.x;
-      gbi += g.y;
+      gbr += g.x, gbi += g.y;
     }
   }
-  gL[(level_off(lp) + P_) * p + m] = make_double2(accr, acci);
-  if (gb && m == 0) gb[level_off(lp) + P_] = make_double2(gbr, gbi);
+  double2 *out = gL + (level_off(lp) + par) * P;
+  double sc = 0.5;  // 2^-(m+1)
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    out[m] = make_double2(sc * sr[m], sc * si[m]);
+    sc *= 0.5;
+  }
+  if (gb) gb[level_off(lp) + par] = make_double2(gbr, gbi);
 }
 
 __global__ void f64_to_f32_kernel(const double *__restrict__ a, float *__restrict__ b, int64_t n) {
@@ -288,13 +333,13 @@ __global__ void l2p_kernel(const float2 *__restrict__ txy, const int32_t *__rest
   const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   const int64_t nleaf = int64_t(1) << (2 * depth);
   if (t >= nt || t >= int64_t(tls[nleaf])) return;
-  const int64_t m = leaf_of(tls, nleaf, t);
+  const float2 z = txy[t];
+  const int64_t m = leaf_of_point(z, tls, nleaf, depth, t);
   uint32_t ix, iy;
   unmorton2(uint32_t(m), ix, iy);
-  const double h = ldexp(1.0, -depth);
-  const float2 z = txy[t];
-  const double wr = (double(z.x) - (double(ix) + 0.5) * h) / h;
-  const double wi = (double(z.y) - (double(iy) + 0.5) * h) / h;
+  const double h = ldexp(1.0, -depth), ih = ldexp(1.0, depth);  // exact
+  const double wr = (double(z.x) - (double(ix) + 0.5) * h) * ih;
+  const double wi = (double(z.y) - (double(iy) + 0.5) * h) * ih;
   const double2 *Ll = L + (level_off(depth) + m) * P;
   double fr = 0.0, fi = 0.0, pr = 0.0, pi = 0.0;
   double cr = 1.0, ci = 0.0;  // w^n
@@ -318,7 +363,7 @@ __global__ void l2p_kernel(const float2 *__restrict__ txy, const int32_t *__rest
   }
   if (field) {
     const float2 o = field[t];
-    field[t] = make_float2(o.x + float(fr / h), o.y + float(fi / h));
+    field[t] = make_float2(o.x + float(fr * ih), o.y + float(fi * ih));
   }
   if (phi) {
     const float2 o = phi[t];
@@ -405,8 +450,13 @@ int launch_p2m_backward(const float *xy, const float *q, const int32_t *ls, int6
 int launch_m2m(float *M, int depth, int p, hipStream_t s) {
   float2 *Mo = reinterpret_cast<float2 *>(M);
   for (int lp = depth - 1; lp >= 0; --lp) {
-    const int64_t work = (int64_t(1) << (2 * lp)) * p;
-    hipLaunchKernelGGL(m2m_kernel, dim3(blocks_for(work)), dim3(256), 0, s, Mo, lp, p);
+    const dim3 g(blocks_for(int64_t(1) << (2 * lp))), bl(256);
+    switch (p) {
+      case 8: hipLaunchKernelGGL(m2m_kernel<8>, g, bl, 0, s, Mo, lp); break;
+      case 12: hipLaunchKernelGGL(m2m_kernel<12>, g, bl, 0, s, Mo, lp); break;
+      case 16: hipLaunchKernelGGL(m2m_kernel<16>, g, bl, 0, s, Mo, lp); break;
+      case 20: hipLaunchKernelGGL(m2m_kernel<20>, g, bl, 0, s, Mo, lp); break;
+    }
   }
   return check_launch("m2m");
 }
@@ -414,8 +464,13 @@ int launch_m2m(float *M, int depth, int p, hipStream_t s) {
 int launch_m2m_backward(float *gM, int depth, int p, hipStream_t s) {
   float2 *g = reinterpret_cast<float2 *>(gM);
   for (int lc = 3; lc <= depth; ++lc) {
-    const int64_t work = (int64_t(1) << (2 * lc)) * p;
-    hipLaunchKernelGGL(m2m_backward_kernel, dim3(blocks_for(work)), dim3(256), 0, s, g, lc, p);
+    const dim3 gr(blocks_for(int64_t(1) << (2 * lc))), bl(256);
+    switch (p) {
+      case 8: hipLaunchKernelGGL(m2m_backward_kernel<8>, gr, bl, 0, s, g, lc); break;
+      case 12: hipLaunchKernelGGL(m2m_backward_kernel<12>, gr, bl, 0, s, g, lc); break;
+      case 16: hipLaunchKernelGGL(m2m_backward_kernel<16>, gr, bl, 0, s, g, lc); break;
+      case 20: hipLaunchKernelGGL(m2m_backward_kernel<20>, gr, bl, 0, s, g, lc); break;
+    }
   }
   return check_launch("m2m_backward");
 }
@@ -430,8 +485,13 @@ int launch_l2l(const float *Lm2l, const float *bm2l, double *L, double *b, int d
   hipLaunchKernelGGL(zero_f64_kernel, dim3(blocks_for(low * p * 2)), dim3(256), 0, s, L, low * p * 2);
   if (b) hipLaunchKernelGGL(zero_f64_kernel, dim3(blocks_for(low * 2)), dim3(256), 0, s, b, low * 2);
   for (int l = 2; l <= depth; ++l) {
-    const int64_t work = (int64_t(1) << (2 * l)) * p;
-    hipLaunchKernelGGL(l2l_kernel, dim3(blocks_for(work)), dim3(256), 0, s, Lm, bm, Lo, bo, l, p);
+    const dim3 g(blocks_for(int64_t(1) << (2 * l))), bl(256);
+    switch (p) {
+      case 8: hipLaunchKernelGGL(l2l_kernel<8>, g, bl, 0, s, Lm, bm, Lo, bo, l); break;
+      case 12: hipLaunchKernelGGL(l2l_kernel<12>, g, bl, 0, s, Lm, bm, Lo, bo, l); break;
+      case 16: hipLaunchKernelGGL(l2l_kernel<16>, g, bl, 0, s, Lm, bm, Lo, bo, l); break;
+      case 20: hipLaunchKernelGGL(l2l_kernel<20>, g, bl, 0, s, Lm, bm, Lo, bo, l); break;
+    }
   }
   return check_launch("l2l");
 }
@@ -440,8 +500,13 @@ int launch_l2l_backward(double *gL, double *gb, float *gLm2l, float *gbm2l, int 
   double2 *g = reinterpret_cast<double2 *>(gL);
   double2 *gbb = reinterpret_cast<double2 *>(gb);
   for (int lp = depth - 1; lp >= 2; --lp) {
-    const int64_t work = (int64_t(1) << (2 * lp)) * p;
-    hipLaunchKernelGGL(l2l_backward_kernel, dim3(blocks_for(work)), dim3(256), 0, s, g, gbb, lp, p);
+    const dim3 gr(blocks_for(int64_t(1) << (2 * lp))), bl(256);
+    switch (p) {
+      case 8: hipLaunchKernelGGL(l2l_backward_kernel<8>, gr, bl, 0, s, g, gbb, lp); break;
+      case 12: hipLaunchKernelGGL(l2l_backward_kernel<12>, gr, bl, 0, s, g, gbb, lp); break;
+      case 16: hipLaunchKernelGGL(l2l_backward_kernel<16>, gr, bl, 0, s, g, gbb, lp); break;
+      case 20: hipLaunchKernelGGL(l2l_backward_kernel<20>, gr, bl, 0, s, g, gbb, lp); break;
+    }
   }
   const int64_t o = level_off(2), e = level_off(depth + 1);
   const int64_t nl = (e - o) * p * 2;

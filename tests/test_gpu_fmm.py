@@ -156,6 +156,30 @@ def test_gradient_matches_oracle(P, n, depth, p):
     del torch
 
 
+@pytest.mark.parametrize("n,depth,p,kind", [(4096, 4, 8, "uniform"), (60000, 6, 16, "mixed"),
+                                            (30000, 5, 20, "mixed")])
+def test_gradient_phi_and_field_matches_oracle(P, n, depth, p, kind):
+    """Linear loss sum Re(w_phi phi + w_f f) with seeded complex weights, so
+    the cotangents are exactly (w_phi, w_f): every transpose, including the
+    field's, against the FP64 oracle's chain at the same tree and p."""
+    print(f"gradient phi+field n={n} depth={depth} p={p}", flush=True)
+    xy = sy.uniform(n, 41) if kind == "uniform" else sy.mixed(n, 41)
+    q = sy.charges(n, 42)
+    t = sy.mixed(3000, 43)
+    g = np.random.Generator(np.random.PCG64(44))
+    wphi = (g.standard_normal(3000) + 1j * g.standard_normal(3000)).astype(np.complex64)
+    wf = (1e-3 * (g.standard_normal(3000) + 1j * g.standard_normal(3000))).astype(np.complex64)
+    xg = _t(xy).requires_grad_(True)
+    qg = _t(q).requires_grad_(True)
+    phi, f = P.potential(xg, qg, _t(t), depth=depth, p=p)
+    loss = (_t(wphi) * phi).real.sum() + (_t(wf) * f).real.sum()
+    loss.backward()
+    gq_r, gxy_r = oracle.fmm_grad(xy.astype(np.float64), q.astype(np.float64), t.astype(np.float64), depth, p,
+                                  wphi.astype(np.complex128), wf.astype(np.complex128))
+    assert rel(qg.grad.cpu().numpy(), gq_r) < 1e-5
+    assert rel(xg.grad.cpu().numpy(), gxy_r) < 1e-5
+
+
 def test_m2l_autograd_matches_adjoint(P):
     """torch.autograd through the M2L Function: grad of Re<w, L> equals the
     conjugated adjoint, checked against the oracle transpose."""
