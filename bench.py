@@ -12,11 +12,16 @@ FP32, with b (the log-potential constant, carried in spare MFMA rows).
 Prints one JSON line with:
   * translations/s, using the exact, boundary-truncated count;
   * Gop/s, at 8p^2 flops per translation;
-  * the roofline of the M2L kernel, timed with HIP events on its stream;
+  * the roofline of the M2L kernel, timed with HIP events on its stream
+    (mean over the timed launches);
+  * launch times one by one after the timed region: warm p10/p50/p90, and
+    cold (caches flushed by a 512 MiB fill before each launch) p50;
   * the adjoint's time;
   * split precision against FP32: the same step in BF16x3 and FP16x3 on this
     workload and on the 2^22-point, depth-9, p = 16 one;
-  * the FP64 oracle's rate on the host cores.
+  * the FP64 oracle's rate on the host cores;
+  * with --fmm, the time of every stage of the whole FMM and of its reverse
+    pass.
 """
 from __future__ import annotations
 
@@ -172,7 +177,41 @@ class Workload:
 
         ms_fwd = timed(lib.fmm2d_m2l, fwd_args, steps, warmup)
         ms_bwd = timed(lib.fmm2d_m2l_backward, bwd_args, max(steps // 2, 1), max(warmup // 2, 1))
+        self._launch = (lib, fwd_args, stream)
         return ms_fwd, ms_bwd
+
+    def launch_spread(self, reps=50, cold_reps=10, flush_bytes=512 << 20):
+        """Forward M2L launch times one by one, after the timed region:
+        warm (back-to-back, operands resident in L2/MALL) as p10/p50/p90, and
+        cold (a 512 MiB fill between launches evicts every cache) as p50."""
+        import torch
+        lib, fwd_args, stream = self._launch
+
+        def one():
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            rc = lib.fmm2d_m2l(*fwd_args)
+            e1.record(stream)
+            if rc != 0:
+                raise RuntimeError(lib.fmm2d_last_error().decode())
+            return e0, e1
+
+        pairs = [one() for _ in range(reps)]
+        torch.cuda.synchronize(self.dev)
+        warm = sorted(a.elapsed_time(b) for a, b in pairs)
+        flush = torch.empty(flush_bytes // 4, dtype=torch.float32, device=self.dev)
+        cold = []
+        for i in range(cold_reps):
+            flush.fill_(float(i))
+            a, b = one()
+            torch.cuda.synchronize(self.dev)
+            cold.append(a.elapsed_time(b))
+        del flush
+        cold.sort()
+        q = lambda v, f: v[min(len(v) - 1, int(f * len(v)))]  # noqa: E731
+        return {"warm_p10": q(warm, 0.1), "warm_p50": q(warm, 0.5), "warm_p90": q(warm, 0.9),
+                "cold_p50": q(cold, 0.5), "warm_reps": reps, "cold_reps": cold_reps}
 
     def level_rel_diff(self, ref_L):
         """max over levels of ||L - ref_L||_F / ||ref_L||_F (device arithmetic)."""
@@ -354,6 +393,7 @@ def main():
                    "translations": w.ntrans, "padded_translations": padded, "seed": args.seed},
         "gop_s": 8.0 * w.p * w.p * w.ntrans / (ms_fwd * 1e-3) / 1e9,
         "roofline": roofline(w, prec_name, ms_fwd),
+        "m2l_launch_ms": w.launch_spread(),
         "adjoint_ms": ms_bwd,
         "adjoint_translations_per_s": w.ntrans / (ms_bwd * 1e-3),
         "adjoint_roofline_frac": roofline(w, prec_name, ms_bwd)["frac"],

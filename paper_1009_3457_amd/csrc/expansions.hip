@@ -381,28 +381,30 @@ __global__ void l2p_backward_kernel(const float2 *__restrict__ txy, const int32_
   if (m >= nleaf) return;
   uint32_t ix, iy;
   unmorton2(uint32_t(m), ix, iy);
-  const double h = ldexp(1.0, -depth);
+  const double h = ldexp(1.0, -depth), ih = ldexp(1.0, depth);  // exact
+  const double cx = (double(ix) + 0.5) * h, cy = (double(iy) + 0.5) * h;
   double ar[P], ai[P];
 #pragma unroll
   for (int n = 0; n < P; ++n) ar[n] = ai[n] = 0.0;
   double sbr = 0.0, sbi = 0.0;
   for (int32_t t = tls[m]; t < tls[m + 1]; ++t) {
     const float2 z = txy[t];
-    const double wr = (double(z.x) - (double(ix) + 0.5) * h) / h;
-    const double wi = (double(z.y) - (double(iy) + 0.5) * h) / h;
+    const double wr = (double(z.x) - cx) * ih, wi = (double(z.y) - cy) * ih;
     const float2 cp = cphi ? cphi[t] : make_float2(0.f, 0.f);
     const float2 cf = cfield ? cfield[t] : make_float2(0.f, 0.f);
+    const double fr = double(cf.x) * ih, fi = double(cf.y) * ih;  // cfield / h
     sbr += cp.x;
     sbi += cp.y;
     double cr = 1.0, ci = 0.0;  // w^n
 #pragma unroll
     for (int n = 0; n < P; ++n) {
-      ar[n] += (cf.x * cr - cf.y * ci) / h;
-      ai[n] += (cf.x * ci + cf.y * cr) / h;
+      ar[n] += fr * cr - fi * ci;
+      ai[n] += fr * ci + fi * cr;
       const double tr = cr * wr - ci * wi;
       ci = cr * wi + ci * wr;
       cr = tr;
-      const double inv = 1.0 / double(n + 1);
+      constexpr double one = 1.0;
+      const double inv = one / double(n + 1);
       ar[n] += inv * (cp.x * cr - cp.y * ci);
       ai[n] += inv * (cp.x * ci + cp.y * cr);
     }

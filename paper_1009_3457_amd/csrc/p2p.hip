@@ -1,20 +1,10 @@
 // Near field (Sec. 2.1, stage 5): direct interactions with the 3x3 block of
 // leaves around each target's leaf, and the transpose for gradients, in FP32
-// arithmetic.  The forward pass runs one wave per target leaf (below); the
-// transpose runs one thread per source.
+// arithmetic.  The forward pass runs one wave per target leaf, the transpose
+// one wave per source leaf.
 #include "fmm2d_internal.h"
 
 namespace fmm2d {
-
-__device__ inline int64_t leaf_of_p2p(const int32_t *__restrict__ ls, int64_t nleaf, int64_t i) {
-  int64_t lo = 0, hi = nleaf;  // invariant: ls[lo] <= i < ls[hi]
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (int64_t(ls[mid]) <= i) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
 
 // atan2(y, x) for (x, y) != (0, 0): octant reduction to a = min/max in
 // [0, 1] and atan(a) = a P(a^2), P an odd degree-15 polynomial fitted here to
@@ -122,54 +112,91 @@ __global__ __launch_bounds__(256) void p2p_kernel(const float2 *__restrict__ xy,
   }
 }
 
-__global__ void p2p_backward_kernel(const float2 *__restrict__ xy, const float *__restrict__ q,
-                                    const int32_t *__restrict__ ls, int64_t n, const float2 *__restrict__ txy,
-                                    const int32_t *__restrict__ tls, int depth, const float2 *__restrict__ cphi,
-                                    const float2 *__restrict__ cfield, float *__restrict__ gq,
-                                    float2 *__restrict__ G) {
-  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+// P2P^T with the same layout: one wave per source leaf, lanes split into
+// NSG sources x NPH target phases over the 3x3 neighbour leaves.  For the
+// pair r = z_t - z_s and cotangents (c, e) of (phi, field) at target t:
+//   dq_s += Re(c log r) + Re(e / r),   G_s += q_s (-c / r + e / r^2),
+// G_s being conj of the position gradient packed as dRe + i dIm.
+template <bool CPHI, bool CF>
+__global__ __launch_bounds__(256) void p2p_backward_kernel(const float2 *__restrict__ xy, const float *__restrict__ q,
+                                                           const int32_t *__restrict__ ls,
+                                                           const float2 *__restrict__ txy,
+                                                           const int32_t *__restrict__ tls, int depth,
+                                                           const float2 *__restrict__ cphi,
+                                                           const float2 *__restrict__ cfield, float *__restrict__ gq,
+                                                           float2 *__restrict__ G) {
   const int64_t nleaf = int64_t(1) << (2 * depth);
-  if (i >= n || i >= int64_t(ls[nleaf])) return;
-  const int64_t m = leaf_of_p2p(ls, nleaf, i);
+  const int64_t leaf = blockIdx.x * int64_t(4) + (threadIdx.x >> 6);
+  if (leaf >= nleaf) return;
+  const int lane = threadIdx.x & 63;
+  const int32_t s0 = ls[leaf], ns = ls[leaf + 1] - s0;
+  if (ns <= 0) return;
   uint32_t ix, iy;
-  unmorton2(uint32_t(m), ix, iy);
+  unmorton2(uint32_t(leaf), ix, iy);
   const int side = 1 << depth;
-  const float2 zs = xy[i];
-  float aqr = 0.f, agr = 0.f, agi = 0.f;
-  for (int dy = -1; dy <= 1; ++dy) {
-    const int ty = int(iy) + dy;
-    if (ty < 0 || ty >= side) continue;
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int tx = int(ix) + dx;
-      if (tx < 0 || tx >= side) continue;
-      const uint32_t tm = morton2(uint32_t(tx), uint32_t(ty));
-      for (int32_t t = tls[tm]; t < tls[tm + 1]; ++t) {
+  int32_t tb[9], te[9];  // target ranges of the 3x3 neighbourhood (empty outside the grid)
+#pragma unroll
+  for (int d = 0; d < 9; ++d) {
+    const int tx = int(ix) + d % 3 - 1, ty = int(iy) + d / 3 - 1;
+    const bool in = tx >= 0 && ty >= 0 && tx < side && ty < side;
+    const uint32_t tm = in ? morton2(uint32_t(tx), uint32_t(ty)) : 0u;
+    tb[d] = in ? tls[tm] : 0;
+    te[d] = in ? tls[tm + 1] : 0;
+  }
+  int nsg = 1;
+  while (nsg < ns && nsg < 64) nsg <<= 1;
+  const int nph = 64 / nsg;
+  const int si = lane & (nsg - 1), ph = lane / nsg;
+  constexpr float kHalfLn2 = 0.346573590279972654709f;  // log(r2) / 2 = kHalfLn2 log2(r2)
+  for (int32_t c0 = 0; c0 < ns; c0 += nsg) {
+    const int32_t sidx = s0 + c0 + si;
+    const bool act = c0 + si < ns;
+    const float2 zs = xy[act ? sidx : s0];
+    float alog = 0.f, aang = 0.f, aq = 0.f, gr = 0.f, gi = 0.f;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) {
+      for (int32_t t = tb[d] + ph; t < te[d]; t += nph) {
         const float2 z = txy[t];
-        const float rx = z.x - zs.x, ry = z.y - zs.y;  // r = z_t - z_s
-        const float r2 = rx * rx + ry * ry;
-        if (r2 == 0.f) continue;
-        const float ir = rx / r2, ii = -ry / r2;  // 1/r
-        if (cphi) {
-          const float2 c = cphi[t];
-          const float lr = 0.5f * logf(r2), li = atan2f(ry, rx);
-          aqr += c.x * lr - c.y * li;
-          agr -= c.x * ir - c.y * ii;
-          agi -= c.x * ii + c.y * ir;
+        const float rx = z.x - zs.x, ry = z.y - zs.y;
+        const float r2 = fmaf(rx, rx, ry * ry);
+        const bool self = r2 == 0.f;  // coincident pair: skipped
+        const float r2s = self ? 1.f : r2;
+        const float inv = __builtin_amdgcn_rcpf(r2s);
+        const float ir = rx * inv, ii = -ry * inv;  // 1/r
+        if (CPHI) {
+          const float2 c0v = cphi[t];
+          const float cx = self ? 0.f : c0v.x, cy = self ? 0.f : c0v.y;
+          alog = fmaf(cx, __builtin_amdgcn_logf(r2s), alog);  // hardware log2
+          aang = fmaf(cy, atan2_p2p(ry, self ? 1.f : rx), aang);
+          gr -= cx * ir - cy * ii;
+          gi -= cx * ii + cy * ir;
         }
-        if (cfield) {
-          const float2 c = cfield[t];
-          aqr += c.x * ir - c.y * ii;
+        if (CF) {
+          const float2 e0 = cfield[t];
+          const float ex = self ? 0.f : e0.x, ey = self ? 0.f : e0.y;
+          aq += ex * ir - ey * ii;
           const float i2r = ir * ir - ii * ii, i2i = 2.f * ir * ii;  // 1/r^2
-          agr += c.x * i2r - c.y * i2i;
-          agi += c.x * i2i + c.y * i2r;
+          gr += ex * i2r - ey * i2i;
+          gi += ex * i2i + ey * i2r;
         }
       }
     }
+    for (int m = nsg; m < 64; m <<= 1) {  // combine the phases: lane ph = 0 ends with the total
+      if (CPHI) {
+        alog += __shfl_xor(alog, m);
+        aang += __shfl_xor(aang, m);
+      }
+      if (CF) aq += __shfl_xor(aq, m);
+      gr += __shfl_xor(gr, m);
+      gi += __shfl_xor(gi, m);
+    }
+    if (act && ph == 0) {
+      const float qs = q[sidx];
+      gq[sidx] += fmaf(kHalfLn2, alog, aq) - aang;
+      const float2 o = G[sidx];
+      G[sidx] = make_float2(fmaf(qs, gr, o.x), fmaf(qs, gi, o.y));
+    }
   }
-  const float qs = q[i];
-  gq[i] += aqr;
-  const float2 o = G[i];
-  G[i] = make_float2(o.x + qs * agr, o.y + qs * agi);
 }
 
 int launch_p2p(const float *xy, const float *q, const int32_t *ls, const float *txy, const int32_t *tls,
@@ -190,11 +217,20 @@ int launch_p2p(const float *xy, const float *q, const int32_t *ls, const float *
 int launch_p2p_backward(const float *xy, const float *q, const int32_t *ls, int64_t n, const float *txy,
                           const int32_t *tls, int depth, const float *cphi, const float *cfield, float *gq, float *G,
                           hipStream_t s) {
-  if (n == 0) return FMM2D_OK;
-  hipLaunchKernelGGL(p2p_backward_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s,
-                     reinterpret_cast<const float2 *>(xy), q, ls, n, reinterpret_cast<const float2 *>(txy), tls,
-                     depth, reinterpret_cast<const float2 *>(cphi), reinterpret_cast<const float2 *>(cfield), gq,
-                     reinterpret_cast<float2 *>(G));
+  if (n == 0 || (!cphi && !cfield)) return FMM2D_OK;
+  const int64_t nleaf = int64_t(1) << (2 * depth);
+  const dim3 grid(unsigned((nleaf + 3) / 4)), block(256);
+  auto X = reinterpret_cast<const float2 *>(xy);
+  auto T = reinterpret_cast<const float2 *>(txy);
+  auto C = reinterpret_cast<const float2 *>(cphi);
+  auto E = reinterpret_cast<const float2 *>(cfield);
+  auto Go = reinterpret_cast<float2 *>(G);
+  if (cphi && cfield)
+    hipLaunchKernelGGL((p2p_backward_kernel<true, true>), grid, block, 0, s, X, q, ls, T, tls, depth, C, E, gq, Go);
+  else if (cphi)
+    hipLaunchKernelGGL((p2p_backward_kernel<true, false>), grid, block, 0, s, X, q, ls, T, tls, depth, C, E, gq, Go);
+  else
+    hipLaunchKernelGGL((p2p_backward_kernel<false, true>), grid, block, 0, s, X, q, ls, T, tls, depth, C, E, gq, Go);
   return check_launch("p2p_backward");
 }
 
