@@ -5,7 +5,8 @@ Only the tests, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 share no code.  Each function below is a thin ctypes wrapper around the plain C
 in ``fmm2d_oracle.c`` (see the citations there), plus the exact power-of-two
 change of basis between the paper's unscaled expansions and the scaled ones the
-GPU library stores.
+GPU library stores.  The fast Gauss transform's Hermite evaluation (Sec. 4.2)
+is in ``fgt2d_oracle.c``, wrapped by ``oracle.fgt``.
 
 Conventions (all arrays numpy):
   * points ``xy`` float64 ``[n, 2]`` (the FP32 inputs promoted exactly);
@@ -23,7 +24,7 @@ import threading
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "fmm2d_oracle.c")
+_SRCS = [os.path.join(_HERE, "fmm2d_oracle.c"), os.path.join(_HERE, "fgt2d_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -35,14 +36,20 @@ _i64 = ctypes.c_int64
 _int = ctypes.c_int
 
 
+def _stale() -> bool:
+    if not os.path.exists(_LIB_PATH):
+        return True
+    built = os.path.getmtime(_LIB_PATH)
+    return any(os.path.getmtime(src) > built for src in _SRCS)
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain -O2, no fast-math) into liboracle.so."""
-    if not force and os.path.exists(_LIB_PATH) and \
-            os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
+    if not force and not _stale():
         return _LIB_PATH
     tmp = _LIB_PATH + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-std=c99", "-O2", "-fno-fast-math", "-ffp-contract=off",
-           "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"]
+           "-fopenmp", "-shared", "-fPIC", *_SRCS, "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -53,8 +60,7 @@ def _load():
     with _lock:
         if _lib is not None:
             return _lib
-        if not os.path.exists(_LIB_PATH) or \
-                os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        if _stale():
             build()
         lib = ctypes.CDLL(_LIB_PATH)
         lib.ora_num_boxes.restype = _i64
@@ -85,6 +91,13 @@ def _load():
         lib.ora_p2m_transpose.argtypes = [_dp, _dp, _i32p, _int, _int, _dp, _dp, _dp]
         lib.ora_direct.argtypes = [_dp, _dp, _i64, _dp, _i64, _dp, _dp]
         lib.ora_direct_grad.argtypes = [_dp, _dp, _i64, _dp, _i64, _dp, _dp, _dp]
+        lib.ora_hermite_functions.argtypes = [ctypes.c_double, _int, _dp]
+        lib.ora_fgt_direct.argtypes = [_dp, _dp, _i64, _dp, _i64, ctypes.c_double, _dp]
+        lib.ora_fgt_direct_boxes.argtypes = [_dp, _dp, _i32p, _int, _dp, _i64, ctypes.c_double,
+                                             _int, _dp]
+        lib.ora_fgt_hermite_coeffs.argtypes = [_dp, _dp, _i32p, _int, _int, ctypes.c_double, _dp]
+        lib.ora_fgt_hermite_eval.argtypes = [_dp, _i64, _int, _int, ctypes.c_double, _int, _dp,
+                                             _dp]
         lib.ora_num_threads.restype = _int
         lib.ora_num_threads.argtypes = []
         lib.ora_init()
