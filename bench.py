@@ -21,7 +21,10 @@ Prints one JSON line with:
     workload and on the 2^22-point, depth-9, p = 16 one;
   * the FP64 oracle's rate on the host cores;
   * with --fmm, the time of every stage of the whole FMM and of its reverse
-    pass.
+    pass;
+  * the fast Gauss transform's Hermite evaluation (Sec. 4.2) at 6,553,600
+    targets, p = 12 (or --fgt W): targets/s, its ALU roofline and the FP64
+    oracle on a sample.
 """
 from __future__ import annotations
 
@@ -52,6 +55,20 @@ MFMA_FLOPS_FACTOR = {"f32": 1, "bf16x3": 3, "f16x3": 3}           # split produc
 PEAK_HBM_GBS = 8000.0
 PAPER_P12_TRANS_PER_S = 80.05e6  # Tesla C1060, p = 12, depth-8 tree (Table tab:m2ltesla)
 
+# Fast Gauss transform, Hermite evaluation: name -> (depth, p, K).  Sources and
+# targets are 100 * 4^depth uniform points each (100 per box, as in the
+# paper's runs: its N are 100 * 4^k), sigma = sqrt(2) 2^-depth (box width
+# r sqrt(2) sigma with r = 1/2), K = 8 boxes each way (cutoff exp(-16)).
+FGT_WORKLOADS = {
+    "fgt_hermite_n6.5M_d8_p12_K8": (8, 12, 8),
+    "fgt_hermite_n6.5M_d8_p9_K8": (8, 9, 8),
+    "fgt_hermite_n6.5M_d8_p5_K8": (8, 5, 8),
+    "fgt_hermite_n25k_d4_p12_K8": (4, 12, 8),
+}
+FGT_DEFAULT = "fgt_hermite_n6.5M_d8_p12_K8"
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PAPER_FGT_PPS = {5: 2.78e7, 9: 6.48e6, 12: 3.27e6}  # Fermi C2050, N = 6,553,600 (Table tab:fgt_results_yeager)
+
 
 def m2l_kernel_sources(precision="f32"):
     """Source files whose text decides the M2L kernel's memory traffic."""
@@ -71,7 +88,13 @@ def source_digest(paths):
     return h.hexdigest()
 
 
-def recorded_traffic(workload, precision):
+def fgt_kernel_sources():
+    """Source files of the Hermite evaluation kernel."""
+    return [os.path.join(ROOT, "paper_1009_3457_amd", "csrc", "fgt.hip"), os.path.join(ROOT, "include", "fgt2d.h"),
+            os.path.join(ROOT, "paper_1009_3457_amd", "csrc", "fmm2d_internal.h")]
+
+
+def recorded_traffic(workload, precision, sources=None):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary,
     or None when it is absent or was taken on different kernel sources."""
     tpath = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
@@ -79,7 +102,7 @@ def recorded_traffic(workload, precision):
         return None
     with open(tpath) as fh:
         rec = json.load(fh)
-    if rec.get("source_sha256") != source_digest(m2l_kernel_sources(precision)):
+    if rec.get("source_sha256") != source_digest(sources or m2l_kernel_sources(precision)):
         return None
     return rec.get("bytes_per_launch")
 
@@ -260,6 +283,92 @@ def mixed_comparison(seed, dev, steps, warmup, main=None):
     return out
 
 
+def fgt_pairs(txy, depth, K):
+    """Exact number of (target, box) pairs: each target takes the boxes within
+    K of its own box in both directions, clipped to the grid."""
+    import numpy as np
+    side = 1 << depth
+    b = np.clip(np.floor(txy.astype(np.float64) * side), 0, side - 1).astype(np.int64)
+    w = np.minimum(b + K, side - 1) - np.maximum(b - K, 0) + 1
+    return int(np.sum(w[:, 0] * w[:, 1]))
+
+
+def fgt_bench(name, seed, dev, steps, warmup, cpu=True, cpu_budget_s=12.0):
+    """The Hermite evaluation of the fast Gauss transform (Sec. 4.2): targets/s
+    over `steps` launches (HIP events on the launch stream, coefficients and
+    sorted targets resident), its ALU roofline, and the FP64 oracle on a
+    sample of the same targets."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import paper_1009_3457_amd as P
+    import synthetic as sy
+    depth, p, K = FGT_WORKLOADS[name]
+    n = 100 * 4 ** depth
+    sigma = float(np.float32(math.sqrt(2.0) * 2.0 ** -depth))
+    xy = torch.from_numpy(sy.uniform(n, seed + 10)).to(dev)
+    q = torch.from_numpy(sy.charges(n, seed + 11)).to(dev)
+    t = torch.from_numpy(sy.uniform(n, seed + 12)).to(dev)
+    perm, ls = P.build_tree(xy, depth)
+    xs, qs = P.gather(xy, perm), P.gather(q, perm)
+    tperm, _ = P.build_tree(t, depth)
+    ts = P.gather(t, tperm)
+    stream = torch.cuda.current_stream(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    A = P.fgt_hermite_coeffs(xs, qs, ls, depth, p, sigma)  # first call loads the code object
+    ev[0].record(stream)
+    A = P.fgt_hermite_coeffs(xs, qs, ls, depth, p, sigma)
+    ev[1].record(stream)
+    G = P.fgt_hermite_eval(ts, depth, p, sigma, K, A)
+    for _ in range(warmup):
+        P.fgt_hermite_eval(ts, depth, p, sigma, K, A, G)
+    torch.cuda.synchronize(dev)
+    ev[2].record(stream)
+    for _ in range(steps):
+        P.fgt_hermite_eval(ts, depth, p, sigma, K, A, G)
+    ev[3].record(stream)
+    torch.cuda.synchronize(dev)
+    ms = ev[2].elapsed_time(ev[3]) / steps
+    ts_np = ts.cpu().numpy()
+    pairs = fgt_pairs(ts_np, depth, K)
+    flops = pairs * (2.0 * p * p + 2.0 * p)
+    tflops = flops / (ms * 1e-3) / 1e12
+    alg_bytes = n * 8 + n * 4 + (1 << (2 * depth)) * p * p * 4
+    out = {
+        "workload": name, "targets": n, "sources": n, "depth": depth, "boxes": 1 << (2 * depth), "p": p, "K": K,
+        "sigma": sigma, "r": 0.5, "pairs": pairs, "ms_per_eval": ms, "targets_per_s": n / (ms * 1e-3),
+        "gflop_s": flops / (ms * 1e-3) / 1e9, "coeffs_ms": ev[0].elapsed_time(ev[1]),
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / PEAK_FP32_VECTOR_TFLOPS,
+                     "traffic": recorded_traffic(name, "f32", fgt_kernel_sources()),
+                     "algorithmic_bytes": alg_bytes},
+        "flops_per_pair": f"2p^2 + 2p = {2 * p * p + 2 * p}",
+        "paper_context": {"targets_per_s": PAPER_FGT_PPS.get(p), "hardware": "Fermi C2050, N = 6,553,600"},
+    }
+    if cpu:
+        import oracle
+        from oracle import fgt as ofgt
+        xs_np, qs_np, ls_np = xs.cpu().numpy(), qs.cpu().numpy(), ls.cpu().numpy()
+        Ar = ofgt.hermite_coeffs(xs_np.astype(np.float64), qs_np.astype(np.float64), ls_np, depth, p, sigma)
+        m, spent = 512, 0.0
+        while True:  # grow the sample until one evaluation takes a few seconds
+            sample = ts_np[:: max(n // m, 1)][:m].astype(np.float64)
+            t0 = time.perf_counter()
+            ofgt.hermite_eval(sample, depth, p, sigma, K, Ar)
+            spent = time.perf_counter() - t0
+            if spent > cpu_budget_s / 4 or m >= n:
+                break
+            m = min(n, int(m * max(2.0, (cpu_budget_s / 4) / max(spent, 1e-3))))
+        out["cpu_baseline"] = {"value": len(sample) / spent, "unit": "targets/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"{len(sample)} of the {n} targets in box order (stride {max(n // m, 1)}), "
+                                         f"FP64 Hermite evaluation with the oracle's coefficients, p={p}, K={K}, "
+                                         f"{spent:.2f} s"}
+    return out
+
+
 def fmm_stage_times(name, prec_name, seed, dev, reps=5):
     """Per-stage times (ms, median of `reps`) of the whole FMM with every point
     as both source and target: tree build (with the sorted gathers), P2M, M2M,
@@ -341,6 +450,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision comparison")
     ap.add_argument("--fmm", action="store_true",
                     help="also time every stage of the whole FMM (all points as sources and targets)")
+    ap.add_argument("--fgt", default=None, choices=sorted(FGT_WORKLOADS),
+                    help="time the fast Gauss transform's Hermite evaluation on this workload "
+                         f"(the default run times {FGT_DEFAULT})")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy, 4 times (reference for "
@@ -405,6 +517,10 @@ def main():
                                                max(args.warmup // 2, 2), main=w)
     if args.fmm:
         out["fmm_stages_ms"] = fmm_stage_times(args.workload, prec_name, args.seed, dev)
+    fgt_name = args.fgt or (FGT_DEFAULT if default_run else None)
+    if fgt_name:
+        out["fgt_hermite"] = fgt_bench(fgt_name, args.seed, dev, max(args.steps // 10, 5),
+                                       max(args.warmup // 10, 2), cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w.M.cpu().numpy(), w.depth, w.p)
     print(json.dumps(out))

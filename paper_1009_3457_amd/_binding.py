@@ -1,4 +1,5 @@
-"""ctypes binding of libfmm2d.so: the C ABI of include/fmm2d.h on torch tensors.
+"""ctypes binding of libfmm2d.so: the C ABI of include/fmm2d.h and
+include/fgt2d.h on torch tensors.
 
 Every function here only marshals arguments (device pointers of contiguous
 tensors, sizes, the current HIP stream) and allocates outputs with torch; all
@@ -52,6 +53,9 @@ _SIGNATURES = {
     "fmm2d_m2m_backward": (_int, [_vp, _int, _int, _vp]),
     "fmm2d_p2m_backward": (_int, [_vp, _vp, _vp, _i64, _int, _int, _vp, _vp, _vp, _vp]),
     "fmm2d_p2p_backward": (_int, [_vp, _vp, _vp, _i64, _vp, _vp, _int, _vp, _vp, _vp, _vp, _vp]),
+    # include/fgt2d.h
+    "fgt2d_hermite_coeffs": (_int, [_vp, _vp, _vp, _int, _int, ctypes.c_float, _vp, _vp]),
+    "fgt2d_hermite_eval": (_int, [_vp, _i64, _int, _int, ctypes.c_float, _int, _vp, _vp, _vp]),
 }
 
 
@@ -293,3 +297,25 @@ def p2p_backward(xy_sorted, q_sorted, leaf_start, txy_sorted, tleaf_start, depth
                                      _p(tleaf_start), depth, _p(cphi), _p(cfield), _p(gq), _p(G),
                                      _stream(dev)))
     return gq, G
+
+
+# ------------------------------------------- fast Gauss transform (FGT) ---
+
+def fgt_hermite_coeffs(xy_sorted, q_sorted, leaf_start, depth: int, p: int, sigma: float):
+    """Hermite coefficients of every box: float32 [4^depth, p, p] ([box, a, b])."""
+    dev = _dev(xy_sorted)
+    A = torch.empty(1 << (2 * depth), p, p, dtype=torch.float32, device=dev)
+    _check(load().fgt2d_hermite_coeffs(_p(xy_sorted), _p(q_sorted), _p(leaf_start), depth, p, float(sigma),
+                                       _p(A), _stream(dev)))
+    return A
+
+
+def fgt_hermite_eval(txy, depth: int, p: int, sigma: float, K: int, A, G=None):
+    """Hermite-series evaluation at the targets txy [nt, 2]: float32 [nt]."""
+    dev = _dev(A)
+    nt = txy.shape[0]
+    if G is None:
+        G = torch.empty(nt, dtype=torch.float32, device=dev)
+    _check(load().fgt2d_hermite_eval(_p(txy), nt, depth, p, float(sigma), int(K), _p(A), _p(G),
+                                     _stream(dev)))
+    return G

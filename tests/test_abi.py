@@ -1,5 +1,5 @@
 """Host-side checks of libfmm2d.so (no GPU needed): every symbol declared in
-include/fmm2d.h is exported, the host-only queries are right, and invalid
+include/fmm2d.h and include/fgt2d.h is exported, the host-only queries are right, and invalid
 arguments are rejected on the host before any HIP call."""
 import ctypes
 import os
@@ -18,9 +18,12 @@ def _lib():
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "fmm2d.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(fmm2d_[a-z0-9_]+)\s*\(", src)))
+    names = set()
+    for header in ("fmm2d.h", "fgt2d.h"):
+        src = open(os.path.join(ROOT, "include", header)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b((?:fmm2d|fgt2d)_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_every_declared_symbol_is_exported():
@@ -118,3 +121,25 @@ def test_split_precision_banks_are_built_for_every_order():
         need = lib.fmm2d_m2l_operators_bytes(16, prec)
         rc = lib.fmm2d_m2l(FAKE, ctypes.c_void_p(0x2000), None, 9, 16, 2, 9, prec, FAKE, need - 1, None)
         assert rc == -5
+
+
+def test_fgt_rejects_bad_arguments_on_host():
+    lib = _lib()
+    f = ctypes.c_float
+    ok = dict(depth=8, sigma=f(0.0055))
+    # coefficients: depth, p, sigma, NULL pointers
+    assert lib.fgt2d_hermite_coeffs(FAKE, FAKE, FAKE, 13, 12, f(0.01), FAKE, None) == -3
+    assert lib.fgt2d_hermite_coeffs(FAKE, FAKE, FAKE, 8, 0, f(0.01), FAKE, None) == -2
+    assert lib.fgt2d_hermite_coeffs(FAKE, FAKE, FAKE, 8, 17, f(0.01), FAKE, None) == -2
+    assert lib.fgt2d_hermite_coeffs(FAKE, FAKE, FAKE, 8, 12, f(0.0), FAKE, None) == -1
+    assert lib.fgt2d_hermite_coeffs(FAKE, FAKE, FAKE, 8, 12, f(float("nan")), FAKE, None) == -1
+    assert lib.fgt2d_hermite_coeffs(FAKE, FAKE, None, 8, 12, f(0.01), FAKE, None) == -1
+    assert "sigma" not in lib.fmm2d_last_error().decode()  # the NULL pointer is what failed
+    # evaluation: nt, K range, NULL pointers; nt = 0 is a no-op
+    assert lib.fgt2d_hermite_eval(FAKE, -1, ok["depth"], 12, ok["sigma"], 8, FAKE, FAKE, None) == -1
+    assert lib.fgt2d_hermite_eval(FAKE, 10, 8, 12, ok["sigma"], -1, FAKE, FAKE, None) == -1
+    assert "K = -1" in lib.fmm2d_last_error().decode()
+    assert lib.fgt2d_hermite_eval(FAKE, 10, 3, 12, ok["sigma"], 8, FAKE, FAKE, None) == -1
+    assert lib.fgt2d_hermite_eval(FAKE, 10, 8, 12, ok["sigma"], 8, None, FAKE, None) == -1
+    assert lib.fgt2d_hermite_eval(None, 10, 8, 12, ok["sigma"], 8, FAKE, FAKE, None) == -1
+    assert lib.fgt2d_hermite_eval(None, 0, 8, 12, ok["sigma"], 8, FAKE, None, None) == 0
