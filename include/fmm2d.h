@@ -76,7 +76,11 @@ typedef enum fmm2d_precision {
     FMM2D_F32 = 0,     /* FP32 products (MFMA f32)                                   */
     FMM2D_BF16X3 = 1,  /* BF16 hi/lo split of both operands, 3 MFMA products (hi*hi,   */
                        /* hi*lo, lo*hi), FP32 accumulation                             */
-    FMM2D_F16X3 = 2    /* the same with FP16 and power-of-two pre-scaling              */
+    FMM2D_F16X3 = 2,   /* the same with FP16 and power-of-two pre-scaling              */
+    FMM2D_F32_PASCAL = 3  /* FP32 products on the factorisation                        */
+                          /*   A~(d) = diag((-1)^n d^-(n+1)) B diag(d^-k),              */
+                          /*   B[n][k] = C(n+k, k): two real MFMA products with the     */
+                          /*   constant B per translation, the diagonals on the VALU   */
 } fmm2d_precision;
 
 /* ----------------------------------------------------------- queries ---- */

@@ -55,7 +55,8 @@ static int check_levels(const char *fn, int depth, int lmin, int lmax) {
 }
 
 static int check_precision(const char *fn, int p, int precision, const void *ops, size_t ops_bytes) {
-  if (precision != FMM2D_F32 && precision != FMM2D_BF16X3 && precision != FMM2D_F16X3)
+  if (precision != FMM2D_F32 && precision != FMM2D_BF16X3 && precision != FMM2D_F16X3 &&
+      precision != FMM2D_F32_PASCAL)
     return set_error(FMM2D_EINVAL, "%s: unknown precision %d", fn, precision);
   const size_t need = m2l_ops_bytes(p, precision);
   if (need == 0)
@@ -184,6 +185,8 @@ static int m2l_common(const char *fn, const float *in, const float *gb_in, float
   FMM2D_NONNULL(fn, out);
   if (in == out) return set_error(FMM2D_EINVAL, "%s: input and output must not overlap", fn);
   if (precision == FMM2D_F32) return launch_m2l_f32(in, gb_in, out, b, depth, p, lmin, lmax, adjoint, ops, stream);
+  if (precision == FMM2D_F32_PASCAL)
+    return launch_m2l_pascal(in, gb_in, out, b, depth, p, lmin, lmax, adjoint, ops, stream);
   return launch_m2l_mixed(in, gb_in, out, b, depth, p, lmin, lmax, adjoint, precision, ops, stream);
 }
 

@@ -97,6 +97,8 @@ size_t m2l_ops_bytes(int p, int precision);
 int launch_m2l_ops(int p, int precision, void *ops, hipStream_t s);
 int launch_m2l_f32(const float *M, const float *gb_in, float *L, float *b, int depth, int p, int lmin, int lmax,
                    bool adjoint, const void *ops, hipStream_t s);
+int launch_m2l_pascal(const float *M, const float *gb_in, float *L, float *b, int depth, int p, int lmin, int lmax,
+                      bool adjoint, const void *ops, hipStream_t s);
 bool m2l_mixed_supported(int p, int precision);
 int num_cus();  // compute units of the current device
 // b(t) for every box of levels lmin..lmax from the forward log rows r[slot][k]

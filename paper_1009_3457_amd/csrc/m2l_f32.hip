@@ -41,6 +41,7 @@
 #include "fmm2d_internal.h"
 #include "m2l_bank.h"
 #include "m2l_common.h"
+#include "m2l_stage.h"
 
 namespace fmm2d {
 
@@ -58,8 +59,8 @@ struct F32Cfg {
   static constexpr int WPC = (P <= 12) ? 1 : 2;    // waves per class
   static constexpr int kThreads = 256 * WPC;
   static constexpr int kWgPerCu = (WPC == 1) ? 2 : 1;
-  static constexpr int kChunks = kRegBoxes * P / 2;                // float4 chunks of a source block
-  static constexpr int kPf = (kChunks + kThreads - 1) / kThreads;  // chunks per thread
+  static constexpr int kChunks = StageCfg<P, kThreads>::kChunks;  // float4 chunks of a source block
+  static constexpr int kPf = StageCfg<P, kThreads>::kPf;           // chunks per thread
   static constexpr int kPfA = (WPC == 1) ? (kPf + 1) / 2 : kPf;  // chunks of the first fetch batch
 };
 
@@ -72,109 +73,6 @@ struct Slice {
   static constexpr int G0 = (WPC == 1) ? 0 : HALF * 4;
   static constexpr int NG = (WPC == 1) ? 7 : (HALF ? 3 : 4);
 };
-
-// Layout of a staged 12x12 source block in LDS, in 16-byte units.  The B
-// fragment of lane (kk, j) for one offset is NE units (2S floats: Re, Im of
-// k = S kk + s) of one box; the 16 lanes of a k-group read a 4x4 window of
-// same-class boxes (stride 2 in the region).  Boxes are therefore stored by
-// class: unit = kRow v' + 6 class + u' with (u', v') = (u, v) / 2, and
-// kRow = 28 = 12 (mod 16) makes the 16 units of any 4x4 window fall on 16
-// distinct 16-byte bank groups, so the reads are free of bank conflicts.
-template <int P>
-struct XLayout {
-  static constexpr int S = P / 4;
-  static constexpr int NE = (2 * S + 3) / 4;  // units per (k-group, box) record
-  static constexpr int kRow = 28;             // 4 classes x 6 + 4 spare units
-  static constexpr int kPlane = 6 * kRow;     // units per (k-group, unit index)
-  static constexpr int kFloats = 4 * NE * kPlane * 4;
-  __device__ static int unit(int kk, int e, int u, int v) {  // u, v in [0, 12)
-    return (kk * NE + e) * kPlane + kRow * (v >> 1) + 6 * ((u & 1) + 2 * (v & 1)) + (u >> 1);
-  }
-};
-
-// Source block of one tile held in registers between the global load and the
-// LDS store.  Every load is issued unconditionally (from box 0 when the box
-// lies outside the grid) and masked when stored, so no branch forces an
-// early wait.
-template <int P>
-struct Prefetch {
-  float4 v[F32Cfg<P>::kPf];
-  float2 g;
-  uint32_t ok;  // bit r: chunk r is inside the grid; bit 31: the gb entry is
-};
-
-struct TileGeo {
-  int level, nside, X0, Y0;
-  int64_t off;
-};
-
-__device__ inline TileGeo tile_geo(const TileMap &map, int t) {
-  TileGeo g;
-  int tile;
-  tile_of(map, t, g.level, tile);
-  g.nside = 1 << g.level;
-  uint32_t tX, tY;
-  unmorton2(uint32_t(tile), tX, tY);
-  g.X0 = int(tX) * kTile;
-  g.Y0 = int(tY) * kTile;
-  g.off = level_off(g.level);
-  return g;
-}
-
-// Loads chunks r0 .. r1-1 (and, with the first batch, the adjoint's gb).
-template <int P, bool ADJ>
-__device__ inline void prefetch_issue(Prefetch<P> &pf, const TileGeo &g, const float2 *__restrict__ X,
-                                      const float2 *__restrict__ gbin, int tid, int r0, int r1) {
-  using C = F32Cfg<P>;
-  if (r0 == 0) pf.ok = 0;
-#pragma unroll
-  for (int r = 0; r < C::kPf; ++r) {
-    if (r < r0 || r >= r1) continue;
-    const int e = tid + C::kThreads * r;
-    const int rb = e / (P / 2), q = e - rb * (P / 2);
-    const int gx = g.X0 - kHalo + rb % kReg, gy = g.Y0 - kHalo + rb / kReg;
-    const bool in = e < C::kChunks && gx >= 0 && gy >= 0 && gx < g.nside && gy < g.nside;
-    const int64_t idx = in ? (g.off + morton2(uint32_t(gx), uint32_t(gy))) * P + 2 * q : 0;
-    pf.v[r] = *reinterpret_cast<const float4 *>(X + idx);
-    pf.ok |= uint32_t(in) << r;
-  }
-  if (ADJ && r0 == 0 && gbin) {  // gbin is uniform
-    const int gx = g.X0 - kHalo + tid % kReg, gy = g.Y0 - kHalo + tid / kReg;
-    const bool in = tid < kRegBoxes && gx >= 0 && gy >= 0 && gx < g.nside && gy < g.nside;
-    pf.g = gbin[in ? g.off + morton2(uint32_t(gx), uint32_t(gy)) : 0];
-    pf.ok |= uint32_t(in) << 31;
-  }
-}
-
-// Stores chunks r0 .. r1-1 into the XLayout buffer (and, with the first
-// batch, gb[box]; entry kRegBoxes of gb stays zero).
-template <int P, bool ADJ>
-__device__ inline void prefetch_store(const Prefetch<P> &pf, float *__restrict__ lx, float2 *__restrict__ lgb,
-                                      int tid, int r0, int r1) {
-  using C = F32Cfg<P>;
-  constexpr int S = C::S;
-#pragma unroll
-  for (int r = 0; r < C::kPf; ++r) {
-    if (r < r0 || r >= r1) continue;
-    const int e = tid + C::kThreads * r;
-    if (e < C::kChunks) {
-      const int rb = e / (P / 2), q = e - rb * (P / 2);
-      const bool in = (pf.ok >> r) & 1u;
-      const float re[2] = {in ? pf.v[r].x : 0.f, in ? pf.v[r].z : 0.f};
-      const float im[2] = {in ? pf.v[r].y : 0.f, in ? pf.v[r].w : 0.f};
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int k = 2 * q + h;
-        const int kk = k / S, s = k - kk * S;
-        const int u = rb % kReg, v = rb / kReg;
-        lx[XLayout<P>::unit(kk, s >> 2, u, v) * 4 + (s & 3)] = re[h];
-        lx[XLayout<P>::unit(kk, (S + s) >> 2, u, v) * 4 + ((S + s) & 3)] = im[h];
-      }
-    }
-  }
-  if (ADJ && r0 == 0 && tid <= kRegBoxes)
-    lgb[tid] = (tid < kRegBoxes && (pf.ok >> 31)) ? pf.g : make_float2(0.f, 0.f);
-}
 
 template <int P, bool ADJ>
 struct LdsF32 {
@@ -288,7 +186,7 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
     const int tn = t + int(gridDim.x);
     const bool has_next = tn < ntiles;
     const TileGeo ngeo = has_next ? tile_geo(map, tn) : geo;
-    Prefetch<P> pf;
+    Prefetch<P, C::kThreads> pf;
     // opaque copy of the thread index: the fetch addresses derived from it
     // are recomputed where used instead of being kept live across the tile
     int ftid = tid;
@@ -365,10 +263,10 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
         }
       }
       if (has_next) {
-        if (i == kIssueA) prefetch_issue<P, ADJ>(pf, ngeo, X, gbin, ftid, 0, C::kPfA);
-        if (i == kStoreA) prefetch_store<P, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], ftid, 0, C::kPfA);
-        if (i == kIssueB) prefetch_issue<P, ADJ>(pf, ngeo, X, gbin, ftid, C::kPfA, C::kPf);
-        if (i == kStoreB) prefetch_store<P, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], ftid, C::kPfA, C::kPf);
+        if (i == kIssueA) prefetch_issue<P, C::kThreads, ADJ>(pf, ngeo, X, gbin, ftid, 0, C::kPfA);
+        if (i == kStoreA) prefetch_store<P, C::kThreads, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], ftid, 0, C::kPfA);
+        if (i == kIssueB) prefetch_issue<P, C::kThreads, ADJ>(pf, ngeo, X, gbin, ftid, C::kPfA, C::kPf);
+        if (i == kStoreB) prefetch_store<P, C::kThreads, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], ftid, C::kPfA, C::kPf);
       }
       // keep the software pipeline as written: operands of offset i+1 are
       // loaded during offset i, not hoisted further (register pressure)
@@ -383,8 +281,8 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
       }
     }
     if (has_next && kIssueB >= NI) {  // second batch not yet issued (short slices)
-      prefetch_issue<P, ADJ>(pf, ngeo, X, gbin, ftid, C::kPfA, C::kPf);
-      prefetch_store<P, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], ftid, C::kPfA, C::kPf);
+      prefetch_issue<P, C::kThreads, ADJ>(pf, ngeo, X, gbin, ftid, C::kPfA, C::kPf);
+      prefetch_store<P, C::kThreads, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], ftid, C::kPfA, C::kPf);
     }
 
     // adjoint log-row part: k-steps over the offset list (B operand = gb)
@@ -557,10 +455,10 @@ __global__ __launch_bounds__(F32Cfg<P>::kThreads, F32Cfg<P>::kWgPerCu) void m2l_
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: class and half in SGPRs
   if (int(blockIdx.x) >= ntiles) return;
   {
-    Prefetch<P> pf;
+    Prefetch<P, C::kThreads> pf;
     const TileGeo g = tile_geo(map, blockIdx.x);
-    prefetch_issue<P, ADJ>(pf, g, X, gbin, tid, 0, C::kPf);
-    prefetch_store<P, ADJ>(pf, sm.x[0], sm.gb[0], tid, 0, C::kPf);
+    prefetch_issue<P, C::kThreads, ADJ>(pf, g, X, gbin, tid, 0, C::kPf);
+    prefetch_store<P, C::kThreads, ADJ>(pf, sm.x[0], sm.gb[0], tid, 0, C::kPf);
     if (ADJ && tid == 0) sm.gb[1][kRegBoxes] = make_float2(0.f, 0.f);
   }
   __syncthreads();

@@ -9,6 +9,7 @@
 #include "fmm2d_internal.h"
 #include "m2l_bank.h"
 #include "m2l_mixed_bank.h"
+#include "m2l_pascal_bank.h"
 
 namespace fmm2d {
 
@@ -112,6 +113,80 @@ __global__ void f32_bank_kernel(float *bank) {
       }
     }
     bank[i] = v;
+  }
+}
+
+// ------------------------------------------------------- Pascal-form bank --
+// d of offset q of class cls for the forward (dir 0: d = -o) or adjoint
+// (dir 1: d = +o) translation; the negation is done on the integers so a zero
+// component is +0 (principal branch of log d).
+__device__ inline cd pascal_d(int dir, int cls, int q) {
+  const int ox = (1 - 2 * (cls & 1)) * kOff00.ox[q], oy = (1 - 2 * (cls >> 1)) * kOff00.oy[q];
+  return dir == 0 ? cd{double(-ox), double(-oy)} : cd{double(ox), double(oy)};
+}
+
+template <int P>
+__global__ void pascal_bank_kernel(float *bank) {
+  using B = PascalBank<P>;
+  using C = PascalCfg<P>;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < B::total_floats; i += stride) {
+    double v = 0.0;
+    if (i < B::bf_off + B::bf_floats) {
+      const size_t e = i - B::bf_off;
+      const int lane = int(e % 64), s = int((e / 64) % C::S), mt = int(e / 64 / C::S);
+      const int n = 16 * mt + lane % 16, k = C::S * (lane / 16) + s;
+      if (n < P) v = binom_f64(n + k, k);
+      else if (C::kLogInRows && n == P) v = k == 0 ? 0.0 : -1.0 / double(k);
+      else if (C::kLogInRows && (n == P + 1 || n == P + 2)) v = k == 0 ? 1.0 : 0.0;
+    } else if (i >= B::tin_off && i < B::tin_off + B::tin_floats) {
+      size_t e = i - B::tin_off;
+      const int pos = int(e % C::LI);
+      e /= C::LI;
+      const int kk = int(e % 4), q = int((e / 4) % 27), cls = int((e / 108) % 4), dir = int(e / 432);
+      if (pos < 2 * C::S) {
+        const int k = C::S * kk + pos / 2;
+        const cd d = pascal_d(dir, cls, q);
+        cd w = cpow_neg(d, dir == 0 ? k : k + 1);
+        if (dir == 1 && (k & 1)) w = {-w.re, -w.im};
+        v = (pos & 1) ? w.im : w.re;
+      }
+    } else if (i >= B::tout_off && i < B::tout_off + B::tout_floats) {
+      size_t e = i - B::tout_off;
+      const int pos = int(e % C::LO);
+      e /= C::LO;
+      const int kk = int(e % 4);
+      e /= 4;
+      const int mt = int(e % C::MT);
+      e /= C::MT;
+      const int q = int(e % 27), cls = int((e / 27) % 4), dir = int(e / 108);
+      const int n = 16 * mt + 4 * kk + pos / 2;
+      const cd d = pascal_d(dir, cls, q);
+      cd w = {0.0, 0.0};
+      if (n < P) {
+        w = cpow_neg(d, dir == 0 ? n + 1 : n);
+        if (dir == 0 && (n & 1)) w = {-w.re, -w.im};
+      } else if (dir == 0 && C::kLogInRows) {
+        if (n == P || n == P + 2) w = {1.0, 0.0};
+        else if (n == P + 1) w = log_row_entry(d.re, d.im, 0);
+      }
+      v = (pos & 1) ? w.im : w.re;
+    } else if (i >= B::lg_off && i < B::lg_off + B::lg_floats) {
+      const size_t e = i - B::lg_off;
+      const int ri = int(e % 2), q = int((e / 2) % 27), cls = int((e / 54) % 4), dir = int(e / 216);
+      const cd d = pascal_d(dir, cls, q);
+      const cd w = log_row_entry(d.re, d.im, 0);
+      v = ri ? w.im : w.re;
+    } else if (i >= B::r_off && i < B::r_off + B::r_floats) {
+      const size_t e = i - B::r_off;
+      const int ri = int(e % 2), k = int((e / 2) % P), slot = int(e / 2 / P);
+      int ox, oy;
+      if (slot_used(slot, ox, oy)) {
+        const cd rv = log_row_entry(double(-ox), double(-oy), k);
+        v = ri ? rv.im : rv.re;
+      }
+    }
+    bank[i] = float(v);
   }
 }
 
@@ -237,11 +312,22 @@ int launch_mixed_ops(int p, int precision, void *ops, hipStream_t s) {
 size_t m2l_ops_bytes(int p, int precision) {
   if (!p_supported(p)) return 0;
   if (precision == FMM2D_F32) return f32_bank_bytes(p);
+  if (precision == FMM2D_F32_PASCAL) return pascal_bank_bytes(p);
   return mixed_bank_bytes(p, precision);
-  return 0;
 }
 
 int launch_m2l_ops(int p, int precision, void *ops, hipStream_t s) {
+  if (precision == FMM2D_F32_PASCAL) {
+    float *bank = static_cast<float *>(ops);
+    dim3 grid(512), block(256);
+    switch (p) {
+      case 8: hipLaunchKernelGGL(pascal_bank_kernel<8>, grid, block, 0, s, bank); break;
+      case 12: hipLaunchKernelGGL(pascal_bank_kernel<12>, grid, block, 0, s, bank); break;
+      case 16: hipLaunchKernelGGL(pascal_bank_kernel<16>, grid, block, 0, s, bank); break;
+      case 20: hipLaunchKernelGGL(pascal_bank_kernel<20>, grid, block, 0, s, bank); break;
+    }
+    return check_launch("m2l Pascal-form operator bank");
+  }
   if (precision != FMM2D_F32) return launch_mixed_ops(p, precision, ops, s);
   float *bank = static_cast<float *>(ops);
   dim3 grid(512), block(256);

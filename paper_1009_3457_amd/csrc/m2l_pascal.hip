@@ -1,0 +1,394 @@
+// FP32 M2L in the Pascal form, with the fused reduction (Sec. 4.1), and its
+// adjoint, on gfx950 matrix cores.
+//
+// The scaled operator factorises exactly (m2l_pascal_bank.h):
+//     A~(d) = D1(d) B D2(d),  B[n][k] = C(n+k, k),  D1 = diag((-1)^n d^-(n+1)),  D2 = diag(d^-k).
+// For each offset of the interaction list the wave scales its staged source
+// coefficients by D2 (VALU), multiplies them by the constant real B (two
+// MFMA chains, one for the real and one for the imaginary parts, on
+// v_mfma_f32_16x16x4_f32 with B's fragments resident in registers for the
+// whole kernel), and adds D1 times the product into the running local
+// expansion (VALU), one offset behind so that it runs under the next
+// offset's matrix products.  Per offset this is 2 p/4 MFMA k-steps per M
+// tile, against 3 p/4 for the Gauss form of the complex product, and the
+// operator occupies p/4 registers per M tile instead of 27 p/2.
+//
+// Work decomposition, staging and prefetch are those of the Gauss-form
+// kernel (m2l_common.h, m2l_stage.h): persistent workgroups of four waves,
+// one per child class, over 8x8 target tiles, two per compute unit.  The reduction over the list runs in a fixed offset
+// order and each L~(t) is written once, so results are bit-reproducible.
+//
+// The log row b rides in rows p .. p+2 of the product when p is not a
+// multiple of 16 (m2l_pascal_bank.h); for p = 16 it is computed by
+// m2l_logrow.hip.  The adjoint applies A~(d)^T = D2(d) B D1(d) over the
+// class's own list with d = +o, and adds the log row's transpose per offset
+// on the VALU: gM~_k += d^-k (Y_k - gb / k) for k >= 1 and
+// gM~_0 += Y_0 + (log d + log h) gb.
+#include "fmm2d_internal.h"
+#include "m2l_bank.h"
+#include "m2l_common.h"
+#include "m2l_pascal_bank.h"
+#include "m2l_stage.h"
+
+namespace fmm2d {
+
+namespace {
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kPThreads = 256;  // one wave per child class
+
+// Where the scaling tables live, chosen per p by measurement.  In LDS
+// (p = 16: all four classes of one direction, 27 KB beside the two staged
+// blocks, 71 KB per workgroup, two workgroups per compute unit) a table read
+// is a broadcast to each lane group of 16.  From the L2-resident bank
+// (p <= 12, and p = 20 whose tables take 48 KB) the workgroup needs only the
+// staged blocks, so three fit per compute unit for p <= 12; the input
+// scalings are then fetched two offsets ahead of their use.
+template <int P>
+struct PascalTab {
+  using C = PascalCfg<P>;
+  static constexpr bool kInLds = P == 16;
+  static constexpr int kIn4 = 27 * 4 * C::LI / 4;          // float4 of one class's "in" records
+  static constexpr int kOut4 = 27 * C::MT * 4 * C::LO / 4;  // float4 of one class's "out" records
+};
+
+template <int P, bool ADJ>
+struct LdsPascal {
+  float x[2][XLayout<P>::kFloats];
+  float2 gb[2][ADJ ? kRegBoxes + 1 : 1];
+  float4 tab[PascalTab<P>::kInLds ? 4 * (PascalTab<P>::kIn4 + PascalTab<P>::kOut4) : 1];
+};
+
+template <int P>
+constexpr int kPascalWgPerCu = P <= 12 ? 3 : 2;
+
+template <int P, bool ADJ, int CX, int CY>
+__device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *__restrict__ X,
+                                           const float2 *__restrict__ gbin, float2 *__restrict__ Y,
+                                           float2 *__restrict__ bout, const float *__restrict__ bank,
+                                           const TileMap &map, int ntiles, int tid) {
+  using C = PascalCfg<P>;
+  using B = PascalBank<P>;
+  using XL = XLayout<P>;
+  using St = StageCfg<P, kPThreads>;
+  using Tb = PascalTab<P>;
+  constexpr int S = C::S, MT = C::MT, LI = C::LI, LO = C::LO, NE = XL::NE;
+  constexpr int cls = CX + 2 * CY, dir = ADJ ? 1 : 0;
+  constexpr int sx = 1 - 2 * CX, sy = 1 - 2 * CY;  // mirror of class (0, 0)'s offsets
+  const int lane = tid & 63;
+  const int j = lane & 15, kk = lane >> 4;
+  const int tx = 2 * (j & 3) + CX, ty = 2 * (j >> 2) + CY;
+
+  // Scaling tables are read through a buffer descriptor: a per-lane VGPR
+  // offset (the lane group's record) plus a scalar offset per offset q.
+  const __amdgpu_buffer_rsrc_t rsrc =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(bank), 0, int(B::total_floats * 4), 0x00020000);
+  auto ld4 = [&](int voff, int soff) {
+    const u32x4_t u = __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, soff, 0);
+    return __builtin_bit_cast(float4, u);
+  };
+  const int vin0 = kk * LI * 4, vout0 = kk * LO * 4;
+
+  // fragments of B, held for the whole kernel
+  float bf[MT][S];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int s = 0; s < S; ++s) bf[mt][s] = bank[B::bf_off + (mt * S + s) * 64 + lane];
+
+  // adjoint: -1/k for this lane's output rows k = 16 mt + 4 kk + r (k = 0: the
+  // log d + log h term is added per offset; rows >= p: zero)
+  float cm[ADJ ? MT : 1][4];
+  if (ADJ) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = 16 * mt + 4 * kk + r;
+        cm[mt][r] = (k >= 1 && k < P) ? -1.f / float(k) : 0.f;
+      }
+  }
+
+  // this lane's unit in the staged block for offset (0, 0) minus the class part
+  const int lbase = (kk * NE * XL::kPlane + XL::kRow * (j >> 2) + (j & 3)) * 4;
+  auto xoff = [&](int i) {  // compile-time after unrolling
+    const int ox = sx * kOff00.ox[i], oy = sy * kOff00.oy[i];
+    const int cu = CX + kHalo + ox, cv = CY + kHalo + oy;  // >= 0
+    return (XL::kRow * (cv >> 1) + 6 * ((cu & 1) + 2 * (cv & 1)) + (cu >> 1)) * 4;
+  };
+  auto gbidx = [&](int i) {
+    return (ty + kHalo + sy * kOff00.oy[i]) * kReg + (tx + kHalo + sx * kOff00.ox[i]);
+  };
+  const float ln2 = 0.69314718055994530942f;
+  constexpr int kIssueA = 1, kStoreA = 12, kIssueB = 13, kStoreB = 24;
+  constexpr int kPfA = (St::kPf + 1) / 2;
+
+  int t = blockIdx.x;
+  TileGeo geo = tile_geo(map, t);
+  int cur = 0;
+  for (;;) {
+    asm volatile("" ::: "memory");  // LDS contents change every tile
+    const int tn = t + int(gridDim.x);
+    const bool has_next = tn < ntiles;
+    const TileGeo ngeo = has_next ? tile_geo(map, tn) : geo;
+    Prefetch<P, kPThreads> pf;
+    int ftid = tid;
+    asm volatile("" : "+v"(ftid));
+    // The scaling tables are the same for every tile; opaque per-tile copies
+    // of their lane offsets keep the compiler from hoisting all 27 offsets'
+    // table loads out of the tile loop (they are loaded where they are used).
+    int vin = vin0, vout = vout0, qin = kk * (LI / 4), qout = kk * (LO / 4);
+    asm volatile("" : "+v"(vin), "+v"(vout), "+v"(qin), "+v"(qout));
+    const float logh = -float(geo.level) * ln2;
+
+    const float *Lb = sm.x[cur];
+    f4_t accr[MT], acci[MT];  // the local expansion (rows 16 mt + 4 kk + r)
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) accr[mt] = acci[mt] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+    float xc[4 * NE], xn[4 * NE];          // staged sources of offset 0, of offset i + 1
+    float ic[LI], in_[LI], in2[LI];        // input scalings of offset 0, i + 1, i + 2
+    float oc[MT][LO], on[MT][LO];          // output scalings of offset i - 1, i
+    float2 gbc = {0.f, 0.f}, gbn = {0.f, 0.f}, lgc = {0.f, 0.f}, lgn = {0.f, 0.f};
+    f4_t pr[2][MT], pim[2][MT];            // products of offsets i (slot i % 2) and i - 1
+
+    auto load_x = [&](float (&dst)[4 * NE], int i) {
+      const float *src = Lb + lbase + xoff(i);
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const float4 v = *reinterpret_cast<const float4 *>(src + e * XL::kPlane * 4);
+        dst[4 * e] = v.x;
+        dst[4 * e + 1] = v.y;
+        dst[4 * e + 2] = v.z;
+        dst[4 * e + 3] = v.w;
+      }
+    };
+    auto load_in = [&](float (&dst)[LI], int i) {
+#pragma unroll
+      for (int e = 0; e < LI / 4; ++e) {
+        const float4 v = Tb::kInLds ? sm.tab[cls * Tb::kIn4 + (i * 4) * (LI / 4) + qin + e]
+                                    : ld4(vin, int(B::tin_rec(dir, cls, i) * 4) + 16 * e);
+        dst[4 * e] = v.x;
+        dst[4 * e + 1] = v.y;
+        dst[4 * e + 2] = v.z;
+        dst[4 * e + 3] = v.w;
+      }
+    };
+    auto load_out = [&](float (&dst)[MT][LO], int i) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int e = 0; e < LO / 4; ++e) {
+          const float4 v = Tb::kInLds
+                               ? sm.tab[4 * Tb::kIn4 + cls * Tb::kOut4 + (i * MT + mt) * 4 * (LO / 4) + qout + e]
+                               : ld4(vout, int(B::tout_rec(dir, cls, i, mt) * 4) + 16 * e);
+          dst[mt][4 * e] = v.x;
+          dst[mt][4 * e + 1] = v.y;
+          dst[mt][4 * e + 2] = v.z;
+          dst[mt][4 * e + 3] = v.w;
+        }
+    };
+    auto load_gb = [&](int i) {
+      const float2 g = sm.gb[cur][gbidx(i)];
+      const float *lgp = bank + B::lg_rec(dir, cls, i);  // uniform: scalar loads
+      return make_float4(g.x, g.y, lgp[0], lgp[1]);
+    };
+    // running sum += D1 (product) for the offset whose scalings are in o
+    auto accumulate = [&](const f4_t (&yr)[MT], const f4_t (&yi)[MT], const float (&o)[MT][LO], float2 g,
+                          float2 lg) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float vr = yr[mt][r], vi = yi[mt][r];
+          if (ADJ) {  // log row's transpose: + c gb, c = -1/k or (log d + log h) at k = 0
+            vr = fmaf(cm[mt][r], g.x, vr);
+            vi = fmaf(cm[mt][r], g.y, vi);
+            if (mt == 0 && r == 0 && kk == 0) {
+              const float cr = lg.x + logh, ci = lg.y;
+              vr = fmaf(cr, g.x, fmaf(-ci, g.y, vr));
+              vi = fmaf(cr, g.y, fmaf(ci, g.x, vi));
+            }
+          }
+          const float dr = o[mt][2 * r], di = o[mt][2 * r + 1];
+          accr[mt][r] = fmaf(dr, vr, fmaf(-di, vi, accr[mt][r]));
+          acci[mt][r] = fmaf(dr, vi, fmaf(di, vr, acci[mt][r]));
+        }
+    };
+
+    // scaled sources of an offset: Re and Im of (input scaling) x, s < S
+    float sr[S], si[S];
+    auto scale = [&](const float (&x)[4 * NE], const float (&c)[LI]) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const float xr = x[s], xi = x[S + s];
+        const float cr = c[2 * s], ci = c[2 * s + 1];
+        sr[s] = fmaf(xr, cr, -xi * ci);
+        si[s] = fmaf(xr, ci, xi * cr);
+      }
+    };
+
+    load_x(xc, 0);
+    load_in(ic, 0);
+    if (!Tb::kInLds) load_in(in2, 1);
+    scale(xc, ic);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+      if (i + 1 < 27) {
+        load_x(xn, i + 1);
+        if (Tb::kInLds) {
+          load_in(in_, i + 1);
+        } else {
+#pragma unroll
+          for (int e = 0; e < LI; ++e) in_[e] = in2[e];
+          if (i + 2 < 27) load_in(in2, i + 2);
+        }
+      }
+      load_out(on, i);
+      if (ADJ) {
+        const float4 g = load_gb(i);
+        gbn = make_float2(g.x, g.y);
+        lgn = make_float2(g.z, g.w);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        f4_t a = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[mt][0], sr[0], f4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+        for (int s = 1; s < S; ++s) a = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[mt][s], sr[s], a, 0, 0, 0);
+        pr[i & 1][mt] = a;
+        f4_t b = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[mt][0], si[0], f4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+        for (int s = 1; s < S; ++s) b = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[mt][s], si[s], b, 0, 0, 0);
+        pim[i & 1][mt] = b;
+      }
+      if (i > 0) accumulate(pr[(i - 1) & 1], pim[(i - 1) & 1], oc, gbc, lgc);
+      // the next offset's operands, under this offset's products
+      if (i + 1 < 27) scale(xn, in_);
+      if (has_next) {
+        if (i == kIssueA) prefetch_issue<P, kPThreads, ADJ>(pf, ngeo, X, gbin, ftid, 0, kPfA);
+        if (i == kStoreA) prefetch_store<P, kPThreads, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], ftid, 0, kPfA);
+        if (i == kIssueB) prefetch_issue<P, kPThreads, ADJ>(pf, ngeo, X, gbin, ftid, kPfA, St::kPf);
+        if (i == kStoreB)
+          prefetch_store<P, kPThreads, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], ftid, kPfA, St::kPf);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      // The running sums feed only the epilogue: without this the compiler
+      // sinks every offset's accumulation toward it, keeping all 27 products
+      // and their scalings live.  Opaque per offset, they are formed here.
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) asm volatile("" : "+v"(accr[mt]), "+v"(acci[mt]));
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int e = 0; e < LO; ++e) oc[mt][e] = on[mt][e];
+      gbc = gbn;
+      lgc = lgn;
+    }
+    accumulate(pr[26 & 1], pim[26 & 1], oc, gbc, lgc);
+
+    const int gx = geo.X0 + tx, gy = geo.Y0 + ty;
+    const bool valid = gx < geo.nside && gy < geo.nside;
+    const int64_t gbox = geo.off + morton2(uint32_t(gx), uint32_t(gy));
+    if (valid) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int n0 = 16 * mt + 4 * kk;
+        if (n0 < P) {
+          float4 *dst = reinterpret_cast<float4 *>(Y + gbox * P + n0);
+          dst[0] = make_float4(accr[mt][0], acci[mt][0], accr[mt][1], acci[mt][1]);
+          dst[1] = make_float4(accr[mt][2], acci[mt][2], accr[mt][3], acci[mt][3]);
+        } else if (!ADJ && C::kLogInRows && n0 == P && bout) {
+          bout[gbox] = make_float2(accr[mt][0] + accr[mt][1] + logh * accr[mt][2],
+                                   acci[mt][0] + acci[mt][1] + logh * acci[mt][2]);
+        }
+      }
+    }
+    // orders the LDS buffers: the next tile's block is complete and this
+    // tile's block is no longer read
+    __syncthreads();
+    if (!has_next) break;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int s = 0; s < S; ++s) asm volatile("" : "+v"(bf[mt][s]));
+    cur ^= 1;
+    t = tn;
+    geo = ngeo;
+  }
+}
+
+template <int P, bool ADJ>
+__global__ __launch_bounds__(kPThreads, kPascalWgPerCu<P>) void m2l_pascal_kernel(const float2 *__restrict__ X,
+                                                                  const float2 *__restrict__ gbin,
+                                                                  float2 *__restrict__ Y, float2 *__restrict__ bout,
+                                                                  const float *__restrict__ bank, TileMap map,
+                                                                  int ntiles) {
+  __shared__ __attribute__((aligned(16))) LdsPascal<P, ADJ> sm;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: the class
+  if (int(blockIdx.x) >= ntiles) return;
+  {
+    Prefetch<P, kPThreads> pf;
+    const TileGeo g = tile_geo(map, blockIdx.x);
+    prefetch_issue<P, kPThreads, ADJ>(pf, g, X, gbin, tid, 0, StageCfg<P, kPThreads>::kPf);
+    if constexpr (PascalTab<P>::kInLds) {  // this direction's scaling tables, all classes
+      using B = PascalBank<P>;
+      using Tb = PascalTab<P>;
+      constexpr int dir = ADJ ? 1 : 0;
+      const float4 *tin = reinterpret_cast<const float4 *>(bank + B::tin_rec(dir, 0, 0));
+      const float4 *tout = reinterpret_cast<const float4 *>(bank + B::tout_rec(dir, 0, 0, 0));
+      for (int e = tid; e < 4 * Tb::kIn4; e += kPThreads) sm.tab[e] = tin[e];
+      for (int e = tid; e < 4 * Tb::kOut4; e += kPThreads) sm.tab[4 * Tb::kIn4 + e] = tout[e];
+    }
+    prefetch_store<P, kPThreads, ADJ>(pf, sm.x[0], sm.gb[0], tid, 0, StageCfg<P, kPThreads>::kPf);
+    if (ADJ && tid == 0) sm.gb[1][kRegBoxes] = make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  // every branch executes the same sequence of barriers; the branch is uniform per wave
+  switch (wave) {
+    case 0: pascal_run<P, ADJ, 0, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+    case 1: pascal_run<P, ADJ, 1, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+    case 2: pascal_run<P, ADJ, 0, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+    default: pascal_run<P, ADJ, 1, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+  }
+}
+
+template <int P>
+void launch_pascal_p(const float *M, const float *gb_in, float *L, float *b, const TileMap &map, int ntiles,
+                     bool adjoint, const void *ops, hipStream_t s) {
+  const int slots = kPascalWgPerCu<P> * num_cus();
+  const int grid = ntiles < slots ? ntiles : slots;
+  const float2 *X = reinterpret_cast<const float2 *>(M);
+  float2 *Y = reinterpret_cast<float2 *>(L);
+  const float *bank = static_cast<const float *>(ops);
+  if (adjoint)
+    hipLaunchKernelGGL((m2l_pascal_kernel<P, true>), dim3(grid), dim3(kPThreads), 0, s, X,
+                       reinterpret_cast<const float2 *>(gb_in), Y, nullptr, bank, map, ntiles);
+  else
+    hipLaunchKernelGGL((m2l_pascal_kernel<P, false>), dim3(grid), dim3(kPThreads), 0, s, X, nullptr, Y,
+                       reinterpret_cast<float2 *>(b), bank, map, ntiles);
+}
+
+}  // namespace
+
+int launch_m2l_pascal(const float *M, const float *gb_in, float *L, float *b, int depth, int p, int lmin, int lmax,
+                      bool adjoint, const void *ops, hipStream_t s) {
+  (void)depth;
+  TileMap map = make_tile_map(lmin, lmax);
+  const int ntiles = map.first[map.nlev];
+  switch (p) {
+    case 8: launch_pascal_p<8>(M, gb_in, L, b, map, ntiles, adjoint, ops, s); break;
+    case 12: launch_pascal_p<12>(M, gb_in, L, b, map, ntiles, adjoint, ops, s); break;
+    case 16: launch_pascal_p<16>(M, gb_in, L, b, map, ntiles, adjoint, ops, s); break;
+    case 20: launch_pascal_p<20>(M, gb_in, L, b, map, ntiles, adjoint, ops, s); break;
+  }
+  int rc = check_launch(adjoint ? "m2l_backward (f32, Pascal form)" : "m2l (f32, Pascal form)");
+  if (rc == FMM2D_OK && !adjoint && b && (p % 16) == 0)  // no spare rows: separate log-row pass
+    rc = launch_m2l_logrow_fwd(M, b, p, lmin, lmax, static_cast<const float *>(ops) + PascalBank<16>::r_off, s);
+  return rc;
+}
+
+}  // namespace fmm2d

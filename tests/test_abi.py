@@ -143,3 +143,14 @@ def test_fgt_rejects_bad_arguments_on_host():
     assert lib.fgt2d_hermite_eval(FAKE, 10, 8, 12, ok["sigma"], 8, None, FAKE, None) == -1
     assert lib.fgt2d_hermite_eval(None, 10, 8, 12, ok["sigma"], 8, FAKE, FAKE, None) == -1
     assert lib.fgt2d_hermite_eval(None, 0, 8, 12, ok["sigma"], 8, FAKE, None, None) == 0
+
+
+def test_pascal_form_banks_are_built_for_every_order():
+    lib = _lib()
+    sizes = [lib.fmm2d_m2l_operators_bytes(p, 3) for p in (8, 12, 16, 20)]
+    assert all(s > 0 for s in sizes) and sizes == sorted(sizes)
+    assert lib.fmm2d_m2l_operators_bytes(10, 3) == 0
+    assert lib.fmm2d_m2l_operators_bytes(12, 4) == 0
+    need = lib.fmm2d_m2l_operators_bytes(12, 3)
+    rc = lib.fmm2d_m2l(FAKE, ctypes.c_void_p(0x2000), None, 8, 12, 2, 8, 3, FAKE, need - 1, None)
+    assert rc == -5
