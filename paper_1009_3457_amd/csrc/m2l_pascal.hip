@@ -15,7 +15,8 @@
 //
 // Work decomposition, staging and prefetch are those of the Gauss-form
 // kernel (m2l_common.h, m2l_stage.h): persistent workgroups of four waves,
-// one per child class, over 8x8 target tiles, two per compute unit.  The reduction over the list runs in a fixed offset
+// one per child class, over 8x8 target tiles, three per compute unit for
+// p <= 16 and two for p = 20 (PascalTab below).  The reduction over the list runs in a fixed offset
 // order and each L~(t) is written once, so results are bit-reproducible.
 //
 // The log row b rides in rows p .. p+2 of the product when p is not a
@@ -39,30 +40,35 @@ typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kPThreads = 256;  // one wave per child class
 
-// Where the scaling tables live, chosen per p by measurement.  In LDS
-// (p = 16: all four classes of one direction, 27 KB beside the two staged
-// blocks, 71 KB per workgroup, two workgroups per compute unit) a table read
-// is a broadcast to each lane group of 16.  From the L2-resident bank
-// (p <= 12, and p = 20 whose tables take 48 KB) the workgroup needs only the
-// staged blocks, so three fit per compute unit for p <= 12; the input
-// scalings are then fetched two offsets ahead of their use.
+// Where the scaling tables live.  For p <= 16 they sit in LDS (all four
+// classes of one direction, 27 KB): a table read is a broadcast to each lane
+// group of 16, and it stays out of the vector-memory counter, which retires
+// loads in issue order, so a table load issued behind the next tile's HBM
+// prefetch would wait for the whole prefetch.  To fit three workgroups per
+// compute unit beside the tables, the source block is then single-buffered:
+// the next tile's block is fetched into registers during the tile and
+// stored between two barriers at its end.  For p = 20 (48 KB of tables) the
+// tables are read from the L2-resident bank, the block is double-buffered as
+// in the Gauss-form kernel, two workgroups per compute unit, and the input
+// scalings are fetched two offsets ahead of their use.
 template <int P>
 struct PascalTab {
   using C = PascalCfg<P>;
-  static constexpr bool kInLds = P == 16;
+  static constexpr bool kInLds = P <= 16;
+  static constexpr int kBufs = kInLds ? 1 : 2;  // staged source blocks
   static constexpr int kIn4 = 27 * 4 * C::LI / 4;          // float4 of one class's "in" records
   static constexpr int kOut4 = 27 * C::MT * 4 * C::LO / 4;  // float4 of one class's "out" records
 };
 
 template <int P, bool ADJ>
 struct LdsPascal {
-  float x[2][XLayout<P>::kFloats];
-  float2 gb[2][ADJ ? kRegBoxes + 1 : 1];
+  float x[PascalTab<P>::kBufs][XLayout<P>::kFloats];
+  float2 gb[PascalTab<P>::kBufs][ADJ ? kRegBoxes + 1 : 1];
   float4 tab[PascalTab<P>::kInLds ? 4 * (PascalTab<P>::kIn4 + PascalTab<P>::kOut4) : 1];
 };
 
 template <int P>
-constexpr int kPascalWgPerCu = P <= 12 ? 3 : 2;
+constexpr int kPascalWgPerCu = P <= 16 ? 3 : 2;
 
 template <int P, bool ADJ, int CX, int CY>
 __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *__restrict__ X,
@@ -268,11 +274,16 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
       // the next offset's operands, under this offset's products
       if (i + 1 < 27) scale(xn, in_);
       if (has_next) {
-        if (i == kIssueA) prefetch_issue<P, kPThreads, ADJ>(pf, ngeo, X, gbin, ftid, 0, kPfA);
-        if (i == kStoreA) prefetch_store<P, kPThreads, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], ftid, 0, kPfA);
-        if (i == kIssueB) prefetch_issue<P, kPThreads, ADJ>(pf, ngeo, X, gbin, ftid, kPfA, St::kPf);
-        if (i == kStoreB)
-          prefetch_store<P, kPThreads, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], ftid, kPfA, St::kPf);
+        if (Tb::kBufs == 1) {  // the whole block at once, stored at the end of the tile
+          if (i == kIssueA) prefetch_issue<P, kPThreads, ADJ>(pf, ngeo, X, gbin, ftid, 0, St::kPf);
+        } else {
+          if (i == kIssueA) prefetch_issue<P, kPThreads, ADJ>(pf, ngeo, X, gbin, ftid, 0, kPfA);
+          if (i == kStoreA)
+            prefetch_store<P, kPThreads, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], ftid, 0, kPfA);
+          if (i == kIssueB) prefetch_issue<P, kPThreads, ADJ>(pf, ngeo, X, gbin, ftid, kPfA, St::kPf);
+          if (i == kStoreB)
+            prefetch_store<P, kPThreads, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], ftid, kPfA, St::kPf);
+        }
       }
       __builtin_amdgcn_sched_barrier(0);
       // The running sums feed only the epilogue: without this the compiler
@@ -306,15 +317,19 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
         }
       }
     }
-    // orders the LDS buffers: the next tile's block is complete and this
-    // tile's block is no longer read
+    // orders the LDS buffers: the next tile's block is complete (two
+    // buffers) or this tile's block is no longer read (one buffer)
     __syncthreads();
     if (!has_next) break;
+    if (Tb::kBufs == 1) {
+      prefetch_store<P, kPThreads, ADJ>(pf, sm.x[0], sm.gb[0], ftid, 0, St::kPf);
+      __syncthreads();
+    }
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int s = 0; s < S; ++s) asm volatile("" : "+v"(bf[mt][s]));
-    cur ^= 1;
+    cur ^= Tb::kBufs - 1;
     t = tn;
     geo = ngeo;
   }
@@ -344,7 +359,7 @@ __global__ __launch_bounds__(kPThreads, kPascalWgPerCu<P>) void m2l_pascal_kerne
       for (int e = tid; e < 4 * Tb::kOut4; e += kPThreads) sm.tab[4 * Tb::kIn4 + e] = tout[e];
     }
     prefetch_store<P, kPThreads, ADJ>(pf, sm.x[0], sm.gb[0], tid, 0, StageCfg<P, kPThreads>::kPf);
-    if (ADJ && tid == 0) sm.gb[1][kRegBoxes] = make_float2(0.f, 0.f);
+    if (ADJ && tid == 0) sm.gb[PascalTab<P>::kBufs - 1][kRegBoxes] = make_float2(0.f, 0.f);
   }
   __syncthreads();
   // every branch executes the same sequence of barriers; the branch is uniform per wave
