@@ -36,35 +36,30 @@ namespace fmm2d {
 namespace {
 
 typedef float f4_t __attribute__((ext_vector_type(4)));
-typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kPThreads = 256;  // one wave per child class
 
-// Where the scaling tables live.  For p <= 16 they sit in LDS (all four
-// classes of one direction, 27 KB): a table read is a broadcast to each lane
-// group of 16, and it stays out of the vector-memory counter, which retires
-// loads in issue order, so a table load issued behind the next tile's HBM
-// prefetch would wait for the whole prefetch.  To fit three workgroups per
-// compute unit beside the tables, the source block is then single-buffered:
-// the next tile's block is fetched into registers during the tile and
-// stored between two barriers at its end.  For p = 20 (48 KB of tables) the
-// tables are read from the L2-resident bank, the block is double-buffered as
-// in the Gauss-form kernel, two workgroups per compute unit, and the input
-// scalings are fetched two offsets ahead of their use.
+// The scaling tables of one direction (all four classes: 27 KB for p <= 16,
+// 48 KB for p = 20) sit in LDS.  A table read is then a broadcast to each
+// lane group of 16, and it stays out of the vector-memory counter, which
+// retires loads in issue order: a table load issued behind the next tile's
+// HBM prefetch would otherwise wait for the whole prefetch.  To fit the
+// tables, the source block is single-buffered: the next tile's block is
+// fetched into registers during the tile and stored between two barriers at
+// its end.  Three workgroups fit per compute unit for p <= 16, two for
+// p = 20 (163.6 of the 160 KiB).
 template <int P>
 struct PascalTab {
   using C = PascalCfg<P>;
-  static constexpr bool kInLds = P <= 16;
-  static constexpr int kBufs = kInLds ? 1 : 2;  // staged source blocks
   static constexpr int kIn4 = 27 * 4 * C::LI / 4;          // float4 of one class's "in" records
   static constexpr int kOut4 = 27 * C::MT * 4 * C::LO / 4;  // float4 of one class's "out" records
 };
 
 template <int P, bool ADJ>
 struct LdsPascal {
-  float x[PascalTab<P>::kBufs][XLayout<P>::kFloats];
-  float2 gb[PascalTab<P>::kBufs][ADJ ? kRegBoxes + 1 : 1];
-  float4 tab[PascalTab<P>::kInLds ? 4 * (PascalTab<P>::kIn4 + PascalTab<P>::kOut4) : 1];
+  float x[XLayout<P>::kFloats];
+  float2 gb[ADJ ? kRegBoxes + 1 : 1];
+  float4 tab[4 * (PascalTab<P>::kIn4 + PascalTab<P>::kOut4)];
 };
 
 template <int P>
@@ -87,15 +82,6 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
   const int j = lane & 15, kk = lane >> 4;
   const int tx = 2 * (j & 3) + CX, ty = 2 * (j >> 2) + CY;
 
-  // Scaling tables are read through a buffer descriptor: a per-lane VGPR
-  // offset (the lane group's record) plus a scalar offset per offset q.
-  const __amdgpu_buffer_rsrc_t rsrc =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(bank), 0, int(B::total_floats * 4), 0x00020000);
-  auto ld4 = [&](int voff, int soff) {
-    const u32x4_t u = __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, soff, 0);
-    return __builtin_bit_cast(float4, u);
-  };
-  const int vin0 = kk * LI * 4, vout0 = kk * LO * 4;
 
   // fragments of B, held for the whole kernel
   float bf[MT][S];
@@ -128,12 +114,10 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
     return (ty + kHalo + sy * kOff00.oy[i]) * kReg + (tx + kHalo + sx * kOff00.ox[i]);
   };
   const float ln2 = 0.69314718055994530942f;
-  constexpr int kIssueA = 1, kStoreA = 12, kIssueB = 13, kStoreB = 24;
-  constexpr int kPfA = (St::kPf + 1) / 2;
+  constexpr int kIssue = 1;  // offset at which the next tile's block is requested
 
   int t = blockIdx.x;
   TileGeo geo = tile_geo(map, t);
-  int cur = 0;
   for (;;) {
     asm volatile("" ::: "memory");  // LDS contents change every tile
     const int tn = t + int(gridDim.x);
@@ -143,19 +127,19 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
     int ftid = tid;
     asm volatile("" : "+v"(ftid));
     // The scaling tables are the same for every tile; opaque per-tile copies
-    // of their lane offsets keep the compiler from hoisting all 27 offsets'
-    // table loads out of the tile loop (they are loaded where they are used).
-    int vin = vin0, vout = vout0, qin = kk * (LI / 4), qout = kk * (LO / 4);
-    asm volatile("" : "+v"(vin), "+v"(vout), "+v"(qin), "+v"(qout));
+    // of the lane group's record index keep the compiler from hoisting all
+    // 27 offsets' table reads out of the tile loop.
+    int qin = kk * (LI / 4), qout = kk * (LO / 4);
+    asm volatile("" : "+v"(qin), "+v"(qout));
     const float logh = -float(geo.level) * ln2;
 
-    const float *Lb = sm.x[cur];
+    const float *Lb = sm.x;
     f4_t accr[MT], acci[MT];  // the local expansion (rows 16 mt + 4 kk + r)
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) accr[mt] = acci[mt] = f4_t{0.f, 0.f, 0.f, 0.f};
 
     float xc[4 * NE], xn[4 * NE];          // staged sources of offset 0, of offset i + 1
-    float ic[LI], in_[LI], in2[LI];        // input scalings of offset 0, i + 1, i + 2
+    float ic[LI], in_[LI];                 // input scalings of offset 0, of offset i + 1
     float oc[MT][LO], on[MT][LO];          // output scalings of offset i - 1, i
     float2 gbc = {0.f, 0.f}, gbn = {0.f, 0.f}, lgc = {0.f, 0.f}, lgn = {0.f, 0.f};
     f4_t pr[2][MT], pim[2][MT];            // products of offsets i (slot i % 2) and i - 1
@@ -174,8 +158,7 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
     auto load_in = [&](float (&dst)[LI], int i) {
 #pragma unroll
       for (int e = 0; e < LI / 4; ++e) {
-        const float4 v = Tb::kInLds ? sm.tab[cls * Tb::kIn4 + (i * 4) * (LI / 4) + qin + e]
-                                    : ld4(vin, int(B::tin_rec(dir, cls, i) * 4) + 16 * e);
+        const float4 v = sm.tab[cls * Tb::kIn4 + (i * 4) * (LI / 4) + qin + e];
         dst[4 * e] = v.x;
         dst[4 * e + 1] = v.y;
         dst[4 * e + 2] = v.z;
@@ -187,9 +170,7 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int e = 0; e < LO / 4; ++e) {
-          const float4 v = Tb::kInLds
-                               ? sm.tab[4 * Tb::kIn4 + cls * Tb::kOut4 + (i * MT + mt) * 4 * (LO / 4) + qout + e]
-                               : ld4(vout, int(B::tout_rec(dir, cls, i, mt) * 4) + 16 * e);
+          const float4 v = sm.tab[4 * Tb::kIn4 + cls * Tb::kOut4 + (i * MT + mt) * 4 * (LO / 4) + qout + e];
           dst[mt][4 * e] = v.x;
           dst[mt][4 * e + 1] = v.y;
           dst[mt][4 * e + 2] = v.z;
@@ -197,7 +178,7 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
         }
     };
     auto load_gb = [&](int i) {
-      const float2 g = sm.gb[cur][gbidx(i)];
+      const float2 g = sm.gb[gbidx(i)];
       const float *lgp = bank + B::lg_rec(dir, cls, i);  // uniform: scalar loads
       return make_float4(g.x, g.y, lgp[0], lgp[1]);
     };
@@ -238,19 +219,12 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
 
     load_x(xc, 0);
     load_in(ic, 0);
-    if (!Tb::kInLds) load_in(in2, 1);
     scale(xc, ic);
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
       if (i + 1 < 27) {
         load_x(xn, i + 1);
-        if (Tb::kInLds) {
-          load_in(in_, i + 1);
-        } else {
-#pragma unroll
-          for (int e = 0; e < LI; ++e) in_[e] = in2[e];
-          if (i + 2 < 27) load_in(in2, i + 2);
-        }
+        load_in(in_, i + 1);
       }
       load_out(on, i);
       if (ADJ) {
@@ -274,16 +248,8 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
       // the next offset's operands, under this offset's products
       if (i + 1 < 27) scale(xn, in_);
       if (has_next) {
-        if (Tb::kBufs == 1) {  // the whole block at once, stored at the end of the tile
-          if (i == kIssueA) prefetch_issue<P, kPThreads, ADJ>(pf, ngeo, X, gbin, ftid, 0, St::kPf);
-        } else {
-          if (i == kIssueA) prefetch_issue<P, kPThreads, ADJ>(pf, ngeo, X, gbin, ftid, 0, kPfA);
-          if (i == kStoreA)
-            prefetch_store<P, kPThreads, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], ftid, 0, kPfA);
-          if (i == kIssueB) prefetch_issue<P, kPThreads, ADJ>(pf, ngeo, X, gbin, ftid, kPfA, St::kPf);
-          if (i == kStoreB)
-            prefetch_store<P, kPThreads, ADJ>(pf, sm.x[cur ^ 1], sm.gb[cur ^ 1], ftid, kPfA, St::kPf);
-        }
+        // the whole next block at once, stored at the end of the tile
+        if (i == kIssue) prefetch_issue<P, kPThreads, ADJ>(pf, ngeo, X, gbin, ftid, 0, St::kPf);
       }
       __builtin_amdgcn_sched_barrier(0);
       // The running sums feed only the epilogue: without this the compiler
@@ -317,19 +283,15 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
         }
       }
     }
-    // orders the LDS buffers: the next tile's block is complete (two
-    // buffers) or this tile's block is no longer read (one buffer)
+    // every wave is done with this tile's block: replace it with the next
     __syncthreads();
     if (!has_next) break;
-    if (Tb::kBufs == 1) {
-      prefetch_store<P, kPThreads, ADJ>(pf, sm.x[0], sm.gb[0], ftid, 0, St::kPf);
-      __syncthreads();
-    }
+    prefetch_store<P, kPThreads, ADJ>(pf, sm.x, sm.gb, ftid, 0, St::kPf);
+    __syncthreads();
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int s = 0; s < S; ++s) asm volatile("" : "+v"(bf[mt][s]));
-    cur ^= Tb::kBufs - 1;
     t = tn;
     geo = ngeo;
   }
@@ -349,7 +311,7 @@ __global__ __launch_bounds__(kPThreads, kPascalWgPerCu<P>) void m2l_pascal_kerne
     Prefetch<P, kPThreads> pf;
     const TileGeo g = tile_geo(map, blockIdx.x);
     prefetch_issue<P, kPThreads, ADJ>(pf, g, X, gbin, tid, 0, StageCfg<P, kPThreads>::kPf);
-    if constexpr (PascalTab<P>::kInLds) {  // this direction's scaling tables, all classes
+    {  // this direction's scaling tables, all classes
       using B = PascalBank<P>;
       using Tb = PascalTab<P>;
       constexpr int dir = ADJ ? 1 : 0;
@@ -358,8 +320,7 @@ __global__ __launch_bounds__(kPThreads, kPascalWgPerCu<P>) void m2l_pascal_kerne
       for (int e = tid; e < 4 * Tb::kIn4; e += kPThreads) sm.tab[e] = tin[e];
       for (int e = tid; e < 4 * Tb::kOut4; e += kPThreads) sm.tab[4 * Tb::kIn4 + e] = tout[e];
     }
-    prefetch_store<P, kPThreads, ADJ>(pf, sm.x[0], sm.gb[0], tid, 0, StageCfg<P, kPThreads>::kPf);
-    if (ADJ && tid == 0) sm.gb[PascalTab<P>::kBufs - 1][kRegBoxes] = make_float2(0.f, 0.f);
+    prefetch_store<P, kPThreads, ADJ>(pf, sm.x, sm.gb, tid, 0, StageCfg<P, kPThreads>::kPf);
   }
   __syncthreads();
   // every branch executes the same sequence of barriers; the branch is uniform per wave
