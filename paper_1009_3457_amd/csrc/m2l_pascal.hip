@@ -311,14 +311,25 @@ __global__ __launch_bounds__(kPThreads, kPascalWgPerCu<P>) void m2l_pascal_kerne
     Prefetch<P, kPThreads> pf;
     const TileGeo g = tile_geo(map, blockIdx.x);
     prefetch_issue<P, kPThreads, ADJ>(pf, g, X, gbin, tid, 0, StageCfg<P, kPThreads>::kPf);
-    {  // this direction's scaling tables, all classes
-      using B = PascalBank<P>;
-      using Tb = PascalTab<P>;
-      constexpr int dir = ADJ ? 1 : 0;
-      const float4 *tin = reinterpret_cast<const float4 *>(bank + B::tin_rec(dir, 0, 0));
-      const float4 *tout = reinterpret_cast<const float4 *>(bank + B::tout_rec(dir, 0, 0, 0));
-      for (int e = tid; e < 4 * Tb::kIn4; e += kPThreads) sm.tab[e] = tin[e];
-      for (int e = tid; e < 4 * Tb::kOut4; e += kPThreads) sm.tab[4 * Tb::kIn4 + e] = tout[e];
+    // this direction's scaling tables, all classes: every chunk is requested
+    // before any is stored, together with the first block, so the prologue
+    // waits for one round trip to L2
+    using B = PascalBank<P>;
+    using Tb = PascalTab<P>;
+    constexpr int dir = ADJ ? 1 : 0, kIn = 4 * Tb::kIn4, kAll = kIn + 4 * Tb::kOut4;
+    constexpr int kPer = (kAll + kPThreads - 1) / kPThreads;
+    const float4 *tin = reinterpret_cast<const float4 *>(bank + B::tin_rec(dir, 0, 0));
+    const float4 *tout = reinterpret_cast<const float4 *>(bank + B::tout_rec(dir, 0, 0, 0));
+    float4 tv[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int e = tid + r * kPThreads;
+      tv[r] = e < kIn ? tin[e] : tout[e < kAll ? e - kIn : 0];
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int e = tid + r * kPThreads;
+      if (e < kAll) sm.tab[e] = tv[r];
     }
     prefetch_store<P, kPThreads, ADJ>(pf, sm.x, sm.gb, tid, 0, StageCfg<P, kPThreads>::kPf);
   }
