@@ -78,6 +78,8 @@ def test_coefficients_match_oracle(P, p):
     (3, 7, 7, 2000, "random"),           # K spans the whole grid
     (1, 4, 1, 500, "random"),
     (0, 6, 0, 300, "sorted"),            # a single box
+    (4, 14, 5, 7777, "random"),          # p not a multiple of 4
+    (2, 13, 3, 999, "sorted"),
 ])
 def test_eval_matches_oracle(P, depth, p, K, nt, order):
     """Evaluation alone: the GPU kernel and the oracle on the same FP32
