@@ -13,9 +13,11 @@ rows).
 
 Prints one JSON line with:
   * translations/s, using the exact, boundary-truncated count;
-  * Gop/s, at 8p^2 flops per translation;
+  * Gop/s, at 8p^2 flops per translation (the dense operator's count, for
+    every form);
   * the roofline of the M2L kernel, timed with HIP events on its stream
-    (mean over the timed launches);
+    (mean over the timed launches), priced at the algorithmic flops of the
+    form the kernel computes (flops_per_translation);
   * launch times one by one after the timed region: warm p10/p50/p90, and
     cold (caches flushed by a 512 MiB fill before each launch) p50;
   * the adjoint's time;
@@ -255,13 +257,30 @@ class Workload:
         return worst
 
 
+def flops_per_translation(p, prec_name, outputs):
+    """Algorithmic flops of one translation in the form the kernel computes.
+
+    Dense operator (Gauss form, split precision): the p x p complex
+    mat-vec, 8p^2, plus 8p for the log row when b is produced; split
+    precision runs three real products per product.  Pascal form: the
+    scaling by D2 (6p), the two real products with B (4p^2) and the scaled
+    accumulation by D1 (8p), plus 4p + 8 for the log row.  Pricing the
+    Pascal form at the dense count would put it above the peak."""
+    with_b = outputs == "Lb"
+    if prec_name == "f32_pascal":
+        return 4 * p * p + 14 * p + (4 * p + 8 if with_b else 0)
+    return (8 * p * p + (8 * p if with_b else 0)) * MFMA_FLOPS_FACTOR[prec_name]
+
+
 def roofline(w, prec_name, ms):
-    flops = 8.0 * w.p * w.p * w.ntrans * MFMA_FLOPS_FACTOR[prec_name]
+    fpt = flops_per_translation(w.p, prec_name, w.outputs)
+    flops = float(fpt) * w.ntrans
     tflops = flops / (ms * 1e-3) / 1e12
     boxes = sum(4 ** l for l in range(2, w.depth + 1))
     alg_bytes = boxes * w.p * 8 * 2 + (boxes * 8 if w.outputs == "Lb" else 0)
     peak = PEAK_TFLOPS[prec_name]
     return {"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s", "frac": tflops / peak,
+            "flops_per_translation": fpt,
             "traffic": recorded_traffic(w.name, prec_name),
             "algorithmic_bytes": alg_bytes,
             "hbm_frac": alg_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}

@@ -65,15 +65,172 @@ struct LdsPascal {
 template <int P>
 constexpr int kPascalWgPerCu = P <= 16 ? 3 : 2;
 
+// ---------------------------------------------------- source block fetch --
+// Target tiles are aligned 8x8 blocks of their level, so every box of a
+// tile's 12x12 source block lies in one of the 3x3 aligned blocks around the
+// tile, at a position inside that block fixed by the box's place in the
+// source block.  The block is fetched in batches (G, q): chunk q (the float4
+// of coefficients 2q, 2q+1) of every box of group G, one box per lane, with
+//   G = 0  the central 8x8 boxes (lane = 8 ly + lx),
+//   G = 1  the four 2x8 edge strips (16 lanes each),
+//   G = 2  the four 2x2 corners (lanes 0..15).
+// A lane's source address is then a wave-uniform block base, formed once per
+// tile on the scalar unit, plus a per-lane constant, with q as an immediate
+// offset; its LDS address is a per-lane constant plus an immediate.  Boxes
+// outside the level read the bank's zero record.  Each wave (one per child
+// class) takes a fixed range of the 3 p / 2 batches, and the adjoint's
+// per-box log-row gradients of group G are fetched by the wave whose range
+// starts group G.
+template <int P>
+struct BlockFetch {
+  static constexpr int Q = P / 2;              // chunks per box record
+  static constexpr int NB = 3 * Q;             // batches per block
+  static constexpr int lo(int w) { return w * NB / 4; }
+  static constexpr int hi(int w) { return (w + 1) * NB / 4; }
+  static constexpr int kMaxB = (NB + 3) / 4;
+  static constexpr bool touches(int w, int g) { return lo(w) < (g + 1) * Q && hi(w) > g * Q; }
+  static constexpr bool owns_gb(int w, int g) { return lo(w) <= g * Q && hi(w) > g * Q; }
+};
+
+// Position (u, v) in the 12x12 source block of the box lane `lane` takes in
+// group g (lanes 16..63 of the corner group repeat lanes 0..15).
+__device__ inline void group_box(int g, int lane, int &u, int &v) {
+  if (g == 0) {
+    u = 2 + (lane & 7);
+    v = 2 + (lane >> 3);
+  } else if (g == 1) {
+    const int e = lane >> 4, a = lane & 1, b = (lane >> 1) & 7;
+    u = e == 0 ? a : e == 1 ? 10 + a : 2 + b;
+    v = e == 0 || e == 1 ? 2 + b : e == 2 ? a : 10 + a;
+  } else {
+    const int c = (lane >> 2) & 3;
+    u = ((c & 1) ? 10 : 0) + (lane & 1);
+    v = ((c >> 1) ? 10 : 0) + ((lane >> 1) & 1);
+  }
+}
+
+// Per-lane constants of the groups a wave fetches.
+template <int P>
+struct LaneBoxes {
+  uint32_t m[3];     // Morton position of the lane's box in its aligned 8x8 block
+  uint32_t lds[3];   // float index in the staged block of the lane's box, unit (kk 0, e 0)
+  uint32_t slot[3];  // v * 12 + u
+  int lx0, ly0;      // the central box's position in its aligned block
+};
+
+template <int P>
+__device__ inline LaneBoxes<P> lane_boxes(int lane) {
+  LaneBoxes<P> c;
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    int u, v;
+    group_box(g, lane, u, v);
+    c.m[g] = morton2(uint32_t((u + 6) & 7), uint32_t((v + 6) & 7));
+    c.lds[g] = uint32_t(XLayout<P>::kRow * (v >> 1) + 6 * ((u & 1) + 2 * (v & 1)) + (u >> 1)) * 4u;
+    c.slot[g] = uint32_t(v * kReg + u);
+  }
+  c.lx0 = lane & 7;
+  c.ly0 = lane >> 3;
+  return c;
+}
+
+template <int P, int W, bool ADJ>
+struct Fetched {
+  static constexpr int B0 = BlockFetch<P>::lo(W), NBW = BlockFetch<P>::hi(W) - B0;
+  float4 v[NBW];
+  float2 g[3];
+};
+
+// Issues the loads of wave W's batches of the block of tile `geo`.
+template <int P, int W, bool ADJ>
+__device__ __forceinline__ void fetch_issue(Fetched<P, W, ADJ> &f, const TileGeo &geo, const float2 *__restrict__ X,
+                                            const float2 *__restrict__ gbin, const float *__restrict__ zero,
+                                            const LaneBoxes<P> &lc, int lane) {
+  using BF = BlockFetch<P>;
+  using F = Fetched<P, W, ADJ>;
+  // wave-uniform: the first box of each of the 3x3 aligned blocks around the
+  // tile, with the neighbours' Morton codes formed from the tile's own by
+  // dilated-integer steps; kNone if the block lies outside the level
+  constexpr uint32_t kEven = 0x55555555u, kOdd = 0xAAAAAAAAu, kNone = ~0u;
+  const int tX = geo.X0 >> 3, tY = geo.Y0 >> 3, nblk = (geo.nside + 7) >> 3;
+  const uint32_t xm = geo.tm & kEven, ym = geo.tm & kOdd;
+  const uint32_t xs[3] = {(xm - 1u) & kEven, xm, ((xm | kOdd) + 1u) & kEven};
+  const uint32_t ys[3] = {(ym - 2u) & kOdd, ym, ((ym | kEven) + 2u) & kOdd};
+  const bool okx[3] = {tX > 0, true, tX + 1 < nblk}, oky[3] = {tY > 0, true, tY + 1 < nblk};
+  const uint32_t off = uint32_t(geo.off);
+  auto block = [&](int cx, int cy) -> uint32_t {
+    return okx[cx + 1] && oky[cy + 1] ? off + ((xs[cx + 1] | ys[cy + 1]) << 6) : kNone;
+  };
+  // the lane's block for group g: g = 1 by lane / 16 (left, right, bottom,
+  // top), g = 2 by (lane / 4) % 4 (the four corners); a level smaller than a
+  // tile has boxes past its side in the central block
+  auto lane_block = [&](int g) -> uint32_t {
+    if (g == 0)
+      return geo.nside < kTile && (lc.lx0 >= geo.nside || lc.ly0 >= geo.nside) ? kNone : block(0, 0);
+    if (g == 1) {
+      const int e = lane >> 4;
+      return e == 0 ? block(-1, 0) : e == 1 ? block(1, 0) : e == 2 ? block(0, -1) : block(0, 1);
+    }
+    const int c = (lane >> 2) & 3;
+    return c == 0 ? block(-1, -1) : c == 1 ? block(1, -1) : c == 2 ? block(-1, 1) : block(1, 1);
+  };
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    if (!BF::touches(W, g)) continue;
+    const uint32_t first = lane_block(g);
+    const bool in = first != kNone;
+    const uint32_t box = first + lc.m[g];
+    const char *a = in ? reinterpret_cast<const char *>(X + size_t(box) * P)
+                       : reinterpret_cast<const char *>(zero) + lc.m[g] * (8u * P);
+#pragma unroll
+    for (int b = F::B0; b < F::B0 + F::NBW; ++b)
+      if (b / BF::Q == g) f.v[b - F::B0] = *reinterpret_cast<const float4 *>(a + 16 * (b % BF::Q));
+    if (ADJ && BF::owns_gb(W, g))
+      f.g[g] = in && gbin ? gbin[box] : *reinterpret_cast<const float2 *>(zero + 2 * lc.m[g]);
+  }
+}
+
+// Stores wave W's batches into the staged block (and the adjoint's
+// gradients of the groups it owns).
+template <int P, int W, bool ADJ>
+__device__ __forceinline__ void fetch_store(const Fetched<P, W, ADJ> &f, float *__restrict__ lx,
+                                            float2 *__restrict__ lgb, const LaneBoxes<P> &lc, int lane) {
+  using BF = BlockFetch<P>;
+  using F = Fetched<P, W, ADJ>;
+  using XL = XLayout<P>;
+  constexpr int S = P / 4;
+#pragma unroll
+  for (int b = F::B0; b < F::B0 + F::NBW; ++b) {
+    const int g = b / BF::Q, q = b % BF::Q;
+    if (g == 2 && lane >= 16) continue;
+    float *dst = lx + lc.lds[g];
+    const float4 c = f.v[b - F::B0];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = 2 * q + h, kk = k / S, sk = k - kk * S;
+      dst[((kk * XL::NE + (sk >> 2)) * XL::kPlane) * 4 + (sk & 3)] = h ? c.z : c.x;
+      dst[((kk * XL::NE + ((S + sk) >> 2)) * XL::kPlane) * 4 + ((S + sk) & 3)] = h ? c.w : c.y;
+    }
+  }
+  if (ADJ) {
+#pragma unroll
+    for (int g = 0; g < 3; ++g)
+      if (BF::owns_gb(W, g) && (g < 2 || lane < 16)) lgb[lc.slot[g]] = f.g[g];
+  }
+}
+
+template <int P>
+constexpr int kTabPer = (4 * (PascalTab<P>::kIn4 + PascalTab<P>::kOut4) + kPThreads - 1) / kPThreads;
+
 template <int P, bool ADJ, int CX, int CY>
 __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *__restrict__ X,
                                            const float2 *__restrict__ gbin, float2 *__restrict__ Y,
                                            float2 *__restrict__ bout, const float *__restrict__ bank,
-                                           const TileMap &map, int ntiles, int tid) {
+                                           const TileMap &map, int ntiles, int tid,
+                                           const float4 (&tv)[kTabPer<P>]) {
   using C = PascalCfg<P>;
   using B = PascalBank<P>;
   using XL = XLayout<P>;
-  using St = StageCfg<P, kPThreads>;
   using Tb = PascalTab<P>;
   constexpr int S = C::S, MT = C::MT, LI = C::LI, LO = C::LO, NE = XL::NE;
   constexpr int cls = CX + 2 * CY, dir = ADJ ? 1 : 0;
@@ -116,21 +273,40 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
   const float ln2 = 0.69314718055994530942f;
   constexpr int kIssue = 1;  // offset at which the next tile's block is requested
 
+  const LaneBoxes<P> lb = lane_boxes<P>(lane);
+  const float *zero = bank + B::zero_off;
   int t = blockIdx.x;
   TileGeo geo = tile_geo(map, t);
+  {
+    // this wave's share of the first block, requested behind the scaling
+    // tables; both are stored once both have arrived
+    Fetched<P, cls, ADJ> f0;
+    fetch_issue<P, cls, ADJ>(f0, geo, X, gbin, zero, lb, lane);
+    constexpr int kAll = 4 * (Tb::kIn4 + Tb::kOut4);
+#pragma unroll
+    for (int r = 0; r < kTabPer<P>; ++r) {
+      const int e = tid + r * kPThreads;
+      if (e < kAll) sm.tab[e] = tv[r];
+    }
+    if (ADJ && cls == 0 && lane == 0) sm.gb[kRegBoxes] = make_float2(0.f, 0.f);  // the empty slot
+    fetch_store<P, cls, ADJ>(f0, sm.x, sm.gb, lb, lane);
+  }
+  __syncthreads();
   for (;;) {
     asm volatile("" ::: "memory");  // LDS contents change every tile
     const int tn = t + int(gridDim.x);
     const bool has_next = tn < ntiles;
     const TileGeo ngeo = has_next ? tile_geo(map, tn) : geo;
-    Prefetch<P, kPThreads> pf;
-    int ftid = tid;
-    asm volatile("" : "+v"(ftid));
+    Fetched<P, cls, ADJ> pf;
     // The scaling tables are the same for every tile; opaque per-tile copies
     // of the lane group's record index keep the compiler from hoisting all
     // 27 offsets' table reads out of the tile loop.
     int qin = kk * (LI / 4), qout = kk * (LO / 4);
     asm volatile("" : "+v"(qin), "+v"(qout));
+    // the adjoint's log d per offset, read with scalar loads: an opaque base
+    // per tile keeps the 27 pairs from being hoisted into scalar registers
+    const float *lgt = bank + B::lg_rec(dir, cls, 0);
+    asm volatile("" : "+s"(lgt));
     const float logh = -float(geo.level) * ln2;
 
     const float *Lb = sm.x;
@@ -179,7 +355,7 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
     };
     auto load_gb = [&](int i) {
       const float2 g = sm.gb[gbidx(i)];
-      const float *lgp = bank + B::lg_rec(dir, cls, i);  // uniform: scalar loads
+      const float *lgp = lgt + 2 * i;  // uniform: scalar loads
       return make_float4(g.x, g.y, lgp[0], lgp[1]);
     };
     // running sum += D1 (product) for the offset whose scalings are in o
@@ -249,8 +425,14 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
       if (i + 1 < 27) scale(xn, in_);
       if (has_next) {
         // the whole next block at once, stored at the end of the tile
-        if (i == kIssue) prefetch_issue<P, kPThreads, ADJ>(pf, ngeo, X, gbin, ftid, 0, St::kPf);
+        if (i == kIssue) fetch_issue<P, cls, ADJ>(pf, ngeo, X, gbin, zero, lb, lane);
       }
+      // FP32 matrix products and vector instructions do not run concurrently
+      // on gfx950, and each switch from one to the other within a wave costs
+      // cycles: the offset's products go first, as one group, then the
+      // vector work.
+      __builtin_amdgcn_sched_group_barrier(0x008, 2 * S * MT, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 1 << 12, 0);
       __builtin_amdgcn_sched_barrier(0);
       // The running sums feed only the epilogue: without this the compiler
       // sinks every offset's accumulation toward it, keeping all 27 products
@@ -286,7 +468,7 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
     // every wave is done with this tile's block: replace it with the next
     __syncthreads();
     if (!has_next) break;
-    prefetch_store<P, kPThreads, ADJ>(pf, sm.x, sm.gb, ftid, 0, St::kPf);
+    fetch_store<P, cls, ADJ>(pf, sm.x, sm.gb, lb, lane);
     __syncthreads();
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -307,39 +489,25 @@ __global__ __launch_bounds__(kPThreads, kPascalWgPerCu<P>) void m2l_pascal_kerne
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: the class
   if (int(blockIdx.x) >= ntiles) return;
-  {
-    Prefetch<P, kPThreads> pf;
-    const TileGeo g = tile_geo(map, blockIdx.x);
-    prefetch_issue<P, kPThreads, ADJ>(pf, g, X, gbin, tid, 0, StageCfg<P, kPThreads>::kPf);
-    // this direction's scaling tables, all classes: every chunk is requested
-    // before any is stored, together with the first block, so the prologue
-    // waits for one round trip to L2
-    using B = PascalBank<P>;
-    using Tb = PascalTab<P>;
-    constexpr int dir = ADJ ? 1 : 0, kIn = 4 * Tb::kIn4, kAll = kIn + 4 * Tb::kOut4;
-    constexpr int kPer = (kAll + kPThreads - 1) / kPThreads;
-    const float4 *tin = reinterpret_cast<const float4 *>(bank + B::tin_rec(dir, 0, 0));
-    const float4 *tout = reinterpret_cast<const float4 *>(bank + B::tout_rec(dir, 0, 0, 0));
-    float4 tv[kPer];
+  // this direction's scaling tables, all classes: requested here and stored
+  // by pascal_run together with the first block
+  using B = PascalBank<P>;
+  using Tb = PascalTab<P>;
+  constexpr int dir = ADJ ? 1 : 0, kIn = 4 * Tb::kIn4, kAll = kIn + 4 * Tb::kOut4;
+  const float4 *tin = reinterpret_cast<const float4 *>(bank + B::tin_rec(dir, 0, 0));
+  const float4 *tout = reinterpret_cast<const float4 *>(bank + B::tout_rec(dir, 0, 0, 0));
+  float4 tv[kTabPer<P>];
 #pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-      const int e = tid + r * kPThreads;
-      tv[r] = e < kIn ? tin[e] : tout[e < kAll ? e - kIn : 0];
-    }
-#pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-      const int e = tid + r * kPThreads;
-      if (e < kAll) sm.tab[e] = tv[r];
-    }
-    prefetch_store<P, kPThreads, ADJ>(pf, sm.x, sm.gb, tid, 0, StageCfg<P, kPThreads>::kPf);
+  for (int r = 0; r < kTabPer<P>; ++r) {
+    const int e = tid + r * kPThreads;
+    tv[r] = e < kIn ? tin[e] : tout[e < kAll ? e - kIn : 0];
   }
-  __syncthreads();
   // every branch executes the same sequence of barriers; the branch is uniform per wave
   switch (wave) {
-    case 0: pascal_run<P, ADJ, 0, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
-    case 1: pascal_run<P, ADJ, 1, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
-    case 2: pascal_run<P, ADJ, 0, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
-    default: pascal_run<P, ADJ, 1, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid); break;
+    case 0: pascal_run<P, ADJ, 0, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid, tv); break;
+    case 1: pascal_run<P, ADJ, 1, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid, tv); break;
+    case 2: pascal_run<P, ADJ, 0, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid, tv); break;
+    default: pascal_run<P, ADJ, 1, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid, tv); break;
   }
 }
 

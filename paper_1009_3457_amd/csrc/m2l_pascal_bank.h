@@ -46,6 +46,8 @@ struct PascalCfg {
 //   tout [dir][cls][q][mt][kk][LO]         forward: D1 and the log rows; adjoint: d^-n (rows < p)
 //   lg   [dir][cls][q][2]                  log d
 //   r    [slot][P][2]                      forward log row r_o (separate b pass, p = 16)
+//   zero [64][P][2]                        zeros: the source record of a box outside
+//                                          the level, for any box position in an 8x8 block
 // dir 0 is the forward translation (d = -o for source t + o of class cls,
 // offset q of the list), dir 1 the adjoint (d = +o, gathered over the
 // class's own list); cls = cx + 2 cy.
@@ -57,12 +59,14 @@ struct PascalBank {
   static constexpr size_t tout_floats = size_t(2) * 4 * 27 * C::MT * 4 * C::LO;
   static constexpr size_t lg_floats = size_t(2) * 4 * 27 * 2;
   static constexpr size_t r_floats = size_t(kSlots) * P * 2;
+  static constexpr size_t zero_floats = size_t(64) * P * 2;
   static constexpr size_t bf_off = 0;
   static constexpr size_t tin_off = (bf_off + bf_floats + 63) / 64 * 64;
   static constexpr size_t tout_off = (tin_off + tin_floats + 63) / 64 * 64;
   static constexpr size_t lg_off = (tout_off + tout_floats + 63) / 64 * 64;
   static constexpr size_t r_off = (lg_off + lg_floats + 63) / 64 * 64;
-  static constexpr size_t total_floats = (r_off + r_floats + 63) / 64 * 64;
+  static constexpr size_t zero_off = (r_off + r_floats + 63) / 64 * 64;
+  static constexpr size_t total_floats = (zero_off + zero_floats + 63) / 64 * 64;
   __host__ __device__ static constexpr size_t tin_rec(int dir, int cls, int q) {
     return tin_off + ((size_t(dir) * 4 + cls) * 27 + q) * 4 * C::LI;
   }

@@ -52,6 +52,7 @@ struct Prefetch {
 struct TileGeo {
   int level, nside, X0, Y0;
   int64_t off;
+  uint32_t tm;  // the tile's Morton index in its level: morton2(X0 / 8, Y0 / 8)
 };
 
 __device__ inline TileGeo tile_geo(const TileMap &map, int t) {
@@ -64,6 +65,7 @@ __device__ inline TileGeo tile_geo(const TileMap &map, int t) {
   g.X0 = int(tX) * kTile;
   g.Y0 = int(tY) * kTile;
   g.off = level_off(g.level);
+  g.tm = uint32_t(tile);
   return g;
 }
 
