@@ -132,13 +132,17 @@ __global__ void pascal_bank_kernel(float *bank) {
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < B::total_floats; i += stride) {
     double v = 0.0;
-    if (i < B::bf_off + B::bf_floats) {
-      const size_t e = i - B::bf_off;
+    if (i < B::bf_off + B::bf_floats || (i >= B::bfp_off && i < B::bfp_off + B::bfp_floats)) {
+      // B, or B' = S1 B S2 for the negative of an offset
+      const bool neg = i >= B::bfp_off;
+      const size_t e = i - (neg ? B::bfp_off : B::bf_off);
       const int lane = int(e % 64), s = int((e / 64) % C::S), mt = int(e / 64 / C::S);
       const int n = 16 * mt + lane % 16, k = C::S * (lane / 16) + s;
-      if (n < P) v = binom_f64(n + k, k);
-      else if (C::kLogInRows && n == P) v = k == 0 ? 0.0 : -1.0 / double(k);
+      const double sk = (k & 1) ? -1.0 : 1.0;
+      if (n < P) v = neg ? -sk * ((n & 1) ? -1.0 : 1.0) * binom_f64(n + k, k) : binom_f64(n + k, k);
+      else if (C::kLogInRows && n == P) v = k == 0 ? 0.0 : (neg ? sk : 1.0) * (-1.0 / double(k));
       else if (C::kLogInRows && (n == P + 1 || n == P + 2)) v = k == 0 ? 1.0 : 0.0;
+      else if (C::kLogInRows && n == P + 3) v = neg && k == 0 ? 1.0 : 0.0;
     } else if (i >= B::tin_off && i < B::tin_off + B::tin_floats) {
       size_t e = i - B::tin_off;
       const int pos = int(e % C::LI);
@@ -167,8 +171,18 @@ __global__ void pascal_bank_kernel(float *bank) {
         w = cpow_neg(d, dir == 0 ? n + 1 : n);
         if (dir == 0 && (n & 1)) w = {-w.re, -w.im};
       } else if (dir == 0 && C::kLogInRows) {
-        if (n == P || n == P + 2) w = {1.0, 0.0};
-        else if (n == P + 1) w = log_row_entry(d.re, d.im, 0);
+        if (n == P || n == P + 2) {
+          w = {1.0, 0.0};
+        } else if (n == P + 1) {
+          w = log_row_entry(d.re, d.im, 0);
+        } else if (n == P + 3 && pascal_partner(q) > q) {
+          // the pair's second offset: log(-d) - log d, +-i pi.  -d is taken
+          // from the partner's own entry, formed from integers like d, so a
+          // zero component is +0 and log(-d) is on the principal branch.
+          const cd d2 = pascal_d(dir, cls, pascal_partner(q));
+          const cd a = log_row_entry(d2.re, d2.im, 0), b = log_row_entry(d.re, d.im, 0);
+          w = {a.re - b.re, a.im - b.im};
+        }
       }
       v = (pos & 1) ? w.im : w.re;
     } else if (i >= B::lg_off && i < B::lg_off + B::lg_floats) {

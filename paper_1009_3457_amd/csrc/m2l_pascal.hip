@@ -19,7 +19,11 @@
 // p <= 16 and two for p = 20 (PascalTab below).  The reduction over the list runs in a fixed offset
 // order and each L~(t) is written once, so results are bit-reproducible.
 //
-// The log row b rides in rows p .. p+2 of the product when p is not a
+// Offsets o and -o of a class's list are taken together (8 pairs of the 27):
+// A~(-d) = D1(d) B' D2(d) with the constant B' = S1 B S2 (m2l_pascal_bank.h),
+// so a pair costs the two products of its offsets but one D1 accumulation.
+//
+// The log row b rides in rows p .. p+3 of the product when p is not a
 // multiple of 16 (m2l_pascal_bank.h); for p = 16 it is computed by
 // m2l_logrow.hip.  The adjoint applies A~(d)^T = D2(d) B D1(d) over the
 // class's own list with d = +o, and adds the log row's transpose per offset
@@ -64,6 +68,12 @@ struct LdsPascal {
 
 template <int P>
 constexpr int kPascalWgPerCu = P <= 16 ? 3 : 2;
+
+// Symmetric offsets taken in pairs (m2l_pascal_bank.h).  A pair holds two
+// staged sources and B' in registers; the adjoints for p = 16 and 20 have no
+// room for them at their occupancy and take every offset alone.
+template <int P, bool ADJ>
+constexpr bool kPascalPairs = !ADJ || P <= 12;
 
 // ---------------------------------------------------- source block fetch --
 // Target tiles are aligned 8x8 blocks of their level, so every box of a
@@ -240,16 +250,20 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
   const int tx = 2 * (j & 3) + CX, ty = 2 * (j >> 2) + CY;
 
 
-  // fragments of B, held for the whole kernel
-  float bf[MT][S];
+  // fragments of B and of B' (pairs only), held for the whole kernel
+  constexpr int SP = kPascalPairs<P, ADJ> ? S : 1;
+  float bf[MT][S], bfp[MT][SP];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
+  for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
     for (int s = 0; s < S; ++s) bf[mt][s] = bank[B::bf_off + (mt * S + s) * 64 + lane];
+#pragma unroll
+    for (int s = 0; s < SP; ++s) bfp[mt][s] = bank[B::bfp_off + (mt * S + s) * 64 + lane];
+  }
 
   // adjoint: -1/k for this lane's output rows k = 16 mt + 4 kk + r (k = 0: the
   // log d + log h term is added per offset; rows >= p: zero)
-  float cm[ADJ ? MT : 1][4];
+  float cm[ADJ ? MT : 1][4], cm2[ADJ ? MT : 1][4];  // cm2: the negative offset's, -(-1)^k / k
   if (ADJ) {
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -257,6 +271,7 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
       for (int r = 0; r < 4; ++r) {
         const int k = 16 * mt + 4 * kk + r;
         cm[mt][r] = (k >= 1 && k < P) ? -1.f / float(k) : 0.f;
+        cm2[mt][r] = (k & 1) ? -cm[mt][r] : cm[mt][r];
       }
   }
 
@@ -288,7 +303,9 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
       const int e = tid + r * kPThreads;
       if (e < kAll) sm.tab[e] = tv[r];
     }
-    if (ADJ && cls == 0 && lane == 0) sm.gb[kRegBoxes] = make_float2(0.f, 0.f);  // the empty slot
+    if constexpr (ADJ) {
+      if (cls == 0 && lane == 0) sm.gb[kRegBoxes] = make_float2(0.f, 0.f);  // the empty slot
+    }
     fetch_store<P, cls, ADJ>(f0, sm.x, sm.gb, lb, lane);
   }
   __syncthreads();
@@ -314,11 +331,18 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) accr[mt] = acci[mt] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-    float xc[4 * NE], xn[4 * NE];          // staged sources of offset 0, of offset i + 1
-    float ic[LI], in_[LI];                 // input scalings of offset 0, of offset i + 1
-    float oc[MT][LO], on[MT][LO];          // output scalings of offset i - 1, i
-    float2 gbc = {0.f, 0.f}, gbn = {0.f, 0.f}, lgc = {0.f, 0.f}, lgn = {0.f, 0.f};
-    f4_t pr[2][MT], pim[2][MT];            // products of offsets i (slot i % 2) and i - 1
+    // A step is one offset, or an offset and its negative (a pair): both
+    // sources are scaled by the same D2 record, their products with B and B'
+    // are summed in the MFMA accumulator, and the step's D1 record is applied
+    // once.  xc/xc2: staged sources of the current step, xn/xn2 of the next.
+    constexpr const PascalSteps &ST = kPascalPairs<P, ADJ> ? kPascalSteps : kPascalSingles;
+    constexpr int NST = ST.n;
+    float xc[4 * NE], xn[4 * NE], xc2[4 * NE], xn2[4 * NE];
+    float ic[LI], in_[LI];                 // input scalings of step 0, of step j + 1
+    float oc[MT][LO], on[MT][LO];          // output scalings of step j - 1, j
+    // adjoint: gb of the step's offsets (x, y: first; z, w: second) and their log d
+    float4 gbc = {0.f, 0.f, 0.f, 0.f}, gbn = gbc, lgc = gbc, lgn = gbc;
+    f4_t pr[2][MT], pim[2][MT];            // products of steps j (slot j % 2) and j - 1
 
     auto load_x = [&](float (&dst)[4 * NE], int i) {
       const float *src = Lb + lbase + xoff(i);
@@ -358,21 +382,30 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
       const float *lgp = lgt + 2 * i;  // uniform: scalar loads
       return make_float4(g.x, g.y, lgp[0], lgp[1]);
     };
-    // running sum += D1 (product) for the offset whose scalings are in o
-    auto accumulate = [&](const f4_t (&yr)[MT], const f4_t (&yi)[MT], const float (&o)[MT][LO], float2 g,
-                          float2 lg) {
+    // running sum += D1 (product) for the step whose scalings are in o
+    auto accumulate = [&](const f4_t (&yr)[MT], const f4_t (&yi)[MT], const float (&o)[MT][LO], float4 g,
+                          float4 lg, bool pair) {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           float vr = yr[mt][r], vi = yi[mt][r];
-          if (ADJ) {  // log row's transpose: + c gb, c = -1/k or (log d + log h) at k = 0
+          if (ADJ) {  // log rows' transposes: + c gb, c = -1/k (k >= 1), (log d + log h) at k = 0
             vr = fmaf(cm[mt][r], g.x, vr);
             vi = fmaf(cm[mt][r], g.y, vi);
+            if (pair) {  // the negative offset's row: -(-1)^k / k
+              vr = fmaf(cm2[mt][r], g.z, vr);
+              vi = fmaf(cm2[mt][r], g.w, vi);
+            }
             if (mt == 0 && r == 0 && kk == 0) {
               const float cr = lg.x + logh, ci = lg.y;
               vr = fmaf(cr, g.x, fmaf(-ci, g.y, vr));
               vi = fmaf(cr, g.y, fmaf(ci, g.x, vi));
+              if (pair) {
+                const float cr2 = lg.z + logh, ci2 = lg.w;
+                vr = fmaf(cr2, g.z, fmaf(-ci2, g.w, vr));
+                vi = fmaf(cr2, g.w, fmaf(ci2, g.z, vi));
+              }
             }
           }
           const float dr = o[mt][2 * r], di = o[mt][2 * r + 1];
@@ -381,32 +414,44 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
         }
     };
 
-    // scaled sources of an offset: Re and Im of (input scaling) x, s < S
-    float sr[S], si[S];
-    auto scale = [&](const float (&x)[4 * NE], const float (&c)[LI]) {
+    // scaled sources of a step: Re and Im of (input scaling) x, s < S
+    float sr[S], si[S], sr2[S], si2[S];
+    auto scale = [&](const float (&x)[4 * NE], const float (&c)[LI], float (&yr)[S], float (&yi)[S]) {
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const float xr = x[s], xi = x[S + s];
         const float cr = c[2 * s], ci = c[2 * s + 1];
-        sr[s] = fmaf(xr, cr, -xi * ci);
-        si[s] = fmaf(xr, ci, xi * cr);
+        yr[s] = fmaf(xr, cr, -xi * ci);
+        yi[s] = fmaf(xr, ci, xi * cr);
       }
     };
 
-    load_x(xc, 0);
-    load_in(ic, 0);
-    scale(xc, ic);
+    load_x(xc, ST.q1[0]);
+    if (ST.q2[0] >= 0) load_x(xc2, ST.q2[0]);
+    load_in(ic, ST.q1[0]);
+    scale(xc, ic, sr, si);
+    if (ST.q2[0] >= 0) scale(xc2, ic, sr2, si2);
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-      if (i + 1 < 27) {
-        load_x(xn, i + 1);
-        load_in(in_, i + 1);
+    for (int j = 0; j < NST; ++j) {
+      const int q1 = ST.q1[j], q2 = ST.q2[j];
+      const bool pair = q2 >= 0;
+      if (j + 1 < NST) {
+        load_x(xn, ST.q1[j + 1]);
+        if (ST.q2[j + 1] >= 0) load_x(xn2, ST.q2[j + 1]);
+        load_in(in_, ST.q1[j + 1]);
       }
-      load_out(on, i);
+      load_out(on, q1);
       if (ADJ) {
-        const float4 g = load_gb(i);
-        gbn = make_float2(g.x, g.y);
-        lgn = make_float2(g.z, g.w);
+        const float4 g = load_gb(q1);
+        gbn = make_float4(g.x, g.y, 0.f, 0.f);
+        lgn = make_float4(g.z, g.w, 0.f, 0.f);
+        if (pair) {
+          const float4 g2 = load_gb(q2);
+          gbn.z = g2.x;
+          gbn.w = g2.y;
+          lgn.z = g2.z;
+          lgn.w = g2.w;
+        }
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -414,29 +459,40 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
         f4_t a = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[mt][0], sr[0], f4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
 #pragma unroll
         for (int s = 1; s < S; ++s) a = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[mt][s], sr[s], a, 0, 0, 0);
-        pr[i & 1][mt] = a;
+        if (pair) {
+#pragma unroll
+          for (int s = 0; s < S; ++s) a = __builtin_amdgcn_mfma_f32_16x16x4f32(bfp[mt][s], sr2[s], a, 0, 0, 0);
+        }
+        pr[j & 1][mt] = a;
         f4_t b = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[mt][0], si[0], f4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
 #pragma unroll
         for (int s = 1; s < S; ++s) b = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[mt][s], si[s], b, 0, 0, 0);
-        pim[i & 1][mt] = b;
+        if (pair) {
+#pragma unroll
+          for (int s = 0; s < S; ++s) b = __builtin_amdgcn_mfma_f32_16x16x4f32(bfp[mt][s], si2[s], b, 0, 0, 0);
+        }
+        pim[j & 1][mt] = b;
       }
-      if (i > 0) accumulate(pr[(i - 1) & 1], pim[(i - 1) & 1], oc, gbc, lgc);
-      // the next offset's operands, under this offset's products
-      if (i + 1 < 27) scale(xn, in_);
+      if (j > 0) accumulate(pr[(j - 1) & 1], pim[(j - 1) & 1], oc, gbc, lgc, ST.q2[j > 0 ? j - 1 : 0] >= 0);
+      // the next step's operands, under this step's products
+      if (j + 1 < NST) {
+        scale(xn, in_, sr, si);
+        if (ST.q2[j + 1] >= 0) scale(xn2, in_, sr2, si2);
+      }
       if (has_next) {
         // the whole next block at once, stored at the end of the tile
-        if (i == kIssue) fetch_issue<P, cls, ADJ>(pf, ngeo, X, gbin, zero, lb, lane);
+        if (j == kIssue) fetch_issue<P, cls, ADJ>(pf, ngeo, X, gbin, zero, lb, lane);
       }
       // FP32 matrix products and vector instructions do not run concurrently
       // on gfx950, and each switch from one to the other within a wave costs
-      // cycles: the offset's products go first, as one group, then the
-      // vector work.
-      __builtin_amdgcn_sched_group_barrier(0x008, 2 * S * MT, 0);
+      // cycles: the step's products go first, as one group, then the vector
+      // work.
+      __builtin_amdgcn_sched_group_barrier(0x008, 4 * S * MT, 0);  // at most: a pair's
       __builtin_amdgcn_sched_group_barrier(0x002, 1 << 12, 0);
       __builtin_amdgcn_sched_barrier(0);
       // The running sums feed only the epilogue: without this the compiler
-      // sinks every offset's accumulation toward it, keeping all 27 products
-      // and their scalings live.  Opaque per offset, they are formed here.
+      // sinks every step's accumulation toward it, keeping all the products
+      // and their scalings live.  Opaque per step, they are formed here.
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) asm volatile("" : "+v"(accr[mt]), "+v"(acci[mt]));
 #pragma unroll
@@ -446,7 +502,7 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
       gbc = gbn;
       lgc = lgn;
     }
-    accumulate(pr[26 & 1], pim[26 & 1], oc, gbc, lgc);
+    accumulate(pr[(NST - 1) & 1], pim[(NST - 1) & 1], oc, gbc, lgc, ST.q2[NST - 1] >= 0);
 
     const int gx = geo.X0 + tx, gy = geo.Y0 + ty;
     const bool valid = gx < geo.nside && gy < geo.nside;
@@ -460,8 +516,8 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
           dst[0] = make_float4(accr[mt][0], acci[mt][0], accr[mt][1], acci[mt][1]);
           dst[1] = make_float4(accr[mt][2], acci[mt][2], accr[mt][3], acci[mt][3]);
         } else if (!ADJ && C::kLogInRows && n0 == P && bout) {
-          bout[gbox] = make_float2(accr[mt][0] + accr[mt][1] + logh * accr[mt][2],
-                                   acci[mt][0] + acci[mt][1] + logh * acci[mt][2]);
+          bout[gbox] = make_float2(accr[mt][0] + accr[mt][1] + accr[mt][3] + logh * accr[mt][2],
+                                   acci[mt][0] + acci[mt][1] + acci[mt][3] + logh * acci[mt][2]);
         }
       }
     }
@@ -471,9 +527,12 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
     fetch_store<P, cls, ADJ>(pf, sm.x, sm.gb, lb, lane);
     __syncthreads();
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
       for (int s = 0; s < S; ++s) asm volatile("" : "+v"(bf[mt][s]));
+#pragma unroll
+      for (int s = 0; s < SP; ++s) asm volatile("" : "+v"(bfp[mt][s]));
+    }
     t = tn;
     geo = ngeo;
   }

@@ -17,10 +17,20 @@
 // and an output scaling ("out" record) the rows 16 mt + 4 (l/16) + r,
 // r < 4, that an MFMA output fragment gives lane l.
 //
-// When p is not a multiple of 16, rows p .. p+2 carry the log-potential
-// constant: B row p = (0, -1/1, -1/2, ...), rows p+1 and p+2 = e_0, with
-// output scalings 1, log d and 1, so that
-//     b = L[p] + L[p+1] + log(h) L[p+2].
+// Symmetric offsets.  With S1 = diag(-(-1)^n) and S2 = diag((-1)^k),
+// D1(-d) = D1(d) S1 and D2(-d) = D2(d) S2, so
+//     A~(-d) = D1(d) B' D2(d),   B' = S1 B S2,  B'[n][k] = -(-1)^(n+k) C(n+k, k).
+// Offsets o and -o that are both in a class's list (8 pairs of its 27) are
+// therefore taken together: both sources are scaled by D2(d), the products
+// B D2 x(t+o) + B' D2 x(t-o) are summed in the MFMA accumulator, and D1(d)
+// is applied once.  The adjoint pairs the same way with B'^T = B'.
+//
+// When p is not a multiple of 16, rows p .. p+3 carry the log-potential
+// constant.  B rows: p = (0, -1/1, -1/2, ...), p+1 = p+2 = e_0, p+3 = 0;
+// B' rows: p = (0, +1/1, -1/2, +1/3, ...) (row p of B times (-1)^k),
+// p+1 = p+2 = p+3 = e_0.  Output scalings 1, log d, 1 and, for a pair,
+// log(-d) - log d (= +-i pi; 0 for a single offset), so that
+//     b = L[p] + L[p+1] + L[p+3] + log(h) L[p+2].
 // For p = 16 the separate b pass reads section r (the forward log rows).
 #pragma once
 
@@ -33,8 +43,8 @@ namespace fmm2d {
 template <int P>
 struct PascalCfg {
   static constexpr int S = P / 4;                      // k-steps of 4
-  static constexpr bool kLogInRows = (P % 16) != 0;    // rows p .. p+2 fit in the last M tile
-  static constexpr int ROWS = P + (kLogInRows ? 3 : 0);
+  static constexpr bool kLogInRows = (P % 16) != 0;    // rows p .. p+3 fit in the last M tile
+  static constexpr int ROWS = P + (kLogInRows ? 4 : 0);
   static constexpr int MT = (ROWS + 15) / 16;          // M tiles of 16 rows
   static constexpr int LI = ((2 * S + 3) / 4) * 4;     // floats of an "in" record (S complex, padded)
   static constexpr int LO = 8;                         // floats of an "out" record (4 complex)
@@ -42,6 +52,7 @@ struct PascalCfg {
 
 // Sections (floats):
 //   bf   [mt][s][lane]                     A fragments of B (rows extended as above)
+//   bfp  [mt][s][lane]                     A fragments of B' (rows extended as above)
 //   tin  [dir][cls][q][kk][LI]             forward: d^-k;        adjoint: (-1)^k d^-(k+1)
 //   tout [dir][cls][q][mt][kk][LO]         forward: D1 and the log rows; adjoint: d^-n (rows < p)
 //   lg   [dir][cls][q][2]                  log d
@@ -55,13 +66,15 @@ template <int P>
 struct PascalBank {
   using C = PascalCfg<P>;
   static constexpr size_t bf_floats = size_t(C::MT) * C::S * 64;
+  static constexpr size_t bfp_floats = bf_floats;
   static constexpr size_t tin_floats = size_t(2) * 4 * 27 * 4 * C::LI;
   static constexpr size_t tout_floats = size_t(2) * 4 * 27 * C::MT * 4 * C::LO;
   static constexpr size_t lg_floats = size_t(2) * 4 * 27 * 2;
   static constexpr size_t r_floats = size_t(kSlots) * P * 2;
   static constexpr size_t zero_floats = size_t(64) * P * 2;
   static constexpr size_t bf_off = 0;
-  static constexpr size_t tin_off = (bf_off + bf_floats + 63) / 64 * 64;
+  static constexpr size_t bfp_off = (bf_off + bf_floats + 63) / 64 * 64;
+  static constexpr size_t tin_off = (bfp_off + bfp_floats + 63) / 64 * 64;
   static constexpr size_t tout_off = (tin_off + tin_floats + 63) / 64 * 64;
   static constexpr size_t lg_off = (tout_off + tout_floats + 63) / 64 * 64;
   static constexpr size_t r_off = (lg_off + lg_floats + 63) / 64 * 64;
@@ -77,6 +90,44 @@ struct PascalBank {
     return lg_off + ((size_t(dir) * 4 + cls) * 27 + q) * 2;
   }
 };
+
+// Offsets of class (0, 0) taken together with their negatives: entry j of
+// the step list is list index q1 alone (q2 < 0) or q1 with q2, o(q2) = -o(q1).
+struct PascalSteps {
+  int n;
+  int q1[27], q2[27];
+};
+
+constexpr PascalSteps make_pascal_steps(bool pairs) {
+  PascalSteps st{};
+  bool used[27] = {};
+  for (int a = 0; a < 27; ++a) {
+    if (used[a]) continue;
+    int partner = -1;
+    for (int b = a + 1; b < 27 && pairs; ++b)
+      if (!used[b] && kOff00.ox[b] == -kOff00.ox[a] && kOff00.oy[b] == -kOff00.oy[a]) partner = b;
+    used[a] = true;
+    if (partner >= 0) used[partner] = true;
+    st.q1[st.n] = a;
+    st.q2[st.n] = partner;
+    ++st.n;
+  }
+  return st;
+}
+
+constexpr PascalSteps kPascalSteps = make_pascal_steps(true);
+constexpr PascalSteps kPascalSingles = make_pascal_steps(false);
+static_assert(kPascalSteps.n == 19, "8 symmetric pairs and 11 single offsets");
+static_assert(kPascalSingles.n == 27, "every offset alone");
+
+// list index of the negative of offset q of class (0, 0), or -1
+__host__ __device__ constexpr int pascal_partner(int q) {
+  for (int j = 0; j < kPascalSteps.n; ++j) {
+    if (kPascalSteps.q1[j] == q) return kPascalSteps.q2[j];
+    if (kPascalSteps.q2[j] == q) return kPascalSteps.q1[j];
+  }
+  return -1;
+}
 
 inline size_t pascal_bank_bytes(int p) {
   switch (p) {

@@ -29,12 +29,34 @@ __device__ inline float atan2_p2p(float y, float x) {
   return copysignf(r, y);
 }
 
-// One wave per target leaf.  The wave's lanes are split into NTG targets x
-// NPH source phases (NTG the leaf's target count rounded up to a power of
-// two, at most 64): lane (i, ph) sums sources ph, ph + NPH, ... of each of
-// the 3x3 neighbour leaves for target i, and the phases are then combined
-// by lane shuffles in a fixed order.  All lanes read the same few sources at
-// a time, so source loads are served once per wave.
+// Lanes of one wave over a chunk of `cnt` (1..64) items (targets of the
+// forward pass, sources of the transpose), each summed over the other side in
+// nph = 64 / cnt phases: lane = ph * cnt + i, and lanes past nph * cnt idle.
+struct ChunkLanes {
+  int cnt, nph, i, ph;
+  __device__ ChunkLanes(int c, int lane) : cnt(c), nph(64 / c), i(lane % c), ph(lane / c) {}
+  __device__ bool active() const { return ph < nph; }
+};
+
+// Sum over the phases of a chunk, in a fixed tree order: lane (i, 0) ends
+// with the total of lanes (i, 0 .. nph-1).
+__device__ inline float phase_sum(float v, const ChunkLanes &c, int lane) {
+  int m = 1;
+  while (2 * m < c.nph) m <<= 1;
+  for (; m >= 1; m >>= 1) {
+    const float o = __shfl(v, lane + m * c.cnt);
+    if (c.ph < m && c.ph + m < c.nph) v += o;
+  }
+  return v;
+}
+
+// One wave per target leaf.  Targets go in chunks of up to 64; the lanes of a
+// chunk of n targets are split into n targets x 64 / n source phases: lane
+// (i, ph) sums sources ph, ph + nph, ... of each of the 3x3 neighbour leaves
+// for target i, and the phases are then combined in a fixed order.  All
+// lanes read the same few sources at a time, so source loads are served once
+// per wave.  Only the target's own leaf can hold a source at the target's
+// position; that pair is skipped.
 template <bool PHI, bool FIELD>
 __global__ __launch_bounds__(256) void p2p_kernel(const float2 *__restrict__ xy, const float *__restrict__ q,
                                                   const int32_t *__restrict__ ls, const float2 *__restrict__ txy,
@@ -58,29 +80,30 @@ __global__ __launch_bounds__(256) void p2p_kernel(const float2 *__restrict__ xy,
     sb[d] = in ? ls[sm] : 0;
     se[d] = in ? ls[sm + 1] : 0;
   }
-  int ntg = 1;
-  while (ntg < nt && ntg < 64) ntg <<= 1;
-  const int nph = 64 / ntg;
-  const int ti = lane & (ntg - 1), ph = lane / ntg;
   constexpr float kHalfLn2 = 0.346573590279972654709f;  // log(r2) / 2 = kHalfLn2 log2(r2)
-  for (int32_t c0 = 0; c0 < nt; c0 += ntg) {
-    const int32_t t = t0 + c0 + ti;
-    const bool act = c0 + ti < nt;
-    const float2 z = txy[act ? t : t0];
+  for (int32_t c0 = 0; c0 < nt; c0 += 64) {
+    const ChunkLanes cl(nt - c0 < 64 ? nt - c0 : 64, lane);
+    const int32_t t = t0 + c0 + cl.i;
+    const bool act = cl.active();
+    const int ph = act ? cl.ph : 0, nph = cl.nph;
+    const float2 z = txy[t];
     float pr = 0.f, pi = 0.f, fr = 0.f, fi = 0.f;
 #pragma unroll
     for (int d = 0; d < 9; ++d) {
-      for (int32_t s = sb[d] + ph; s < se[d]; s += nph) {
+      for (int32_t s = act ? sb[d] + ph : se[d]; s < se[d]; s += nph) {
         const float2 zs = xy[s];
-        const float qs0 = q[s];
         const float rx = z.x - zs.x, ry = z.y - zs.y;
         const float r2 = fmaf(rx, rx, ry * ry);
-        const bool self = r2 == 0.f;  // coincident pair: skipped
-        const float qs = self ? 0.f : qs0;
-        const float r2s = self ? 1.f : r2;
+        float qs = q[s], r2s = r2, ax = rx;
+        if (d == 4) {  // own leaf: a coincident pair is skipped
+          const bool self = r2 == 0.f;
+          qs = self ? 0.f : qs;
+          r2s = self ? 1.f : r2;
+          ax = self ? 1.f : rx;
+        }
         if (PHI) {
           pr = fmaf(qs, __builtin_amdgcn_logf(r2s), pr);  // hardware log2
-          pi = fmaf(qs, atan2_p2p(ry, self ? 1.f : rx), pi);
+          pi = fmaf(qs, atan2_p2p(ry, ax), pi);
         }
         if (FIELD) {
           const float inv = qs * __builtin_amdgcn_rcpf(r2s);  // hardware reciprocal (1 ulp)
@@ -89,17 +112,17 @@ __global__ __launch_bounds__(256) void p2p_kernel(const float2 *__restrict__ xy,
         }
       }
     }
-    for (int m = ntg; m < 64; m <<= 1) {  // combine the phases: lane ph = 0 ends with the total
+    if (nph > 1) {  // combine the phases: lane ph = 0 ends with the total
       if (PHI) {
-        pr += __shfl_xor(pr, m);
-        pi += __shfl_xor(pi, m);
+        pr = phase_sum(pr, cl, lane);
+        pi = phase_sum(pi, cl, lane);
       }
       if (FIELD) {
-        fr += __shfl_xor(fr, m);
-        fi += __shfl_xor(fi, m);
+        fr = phase_sum(fr, cl, lane);
+        fi = phase_sum(fi, cl, lane);
       }
     }
-    if (act && ph == 0) {
+    if (act && cl.ph == 0) {
       if (PHI) {
         const float2 o = phi[t];
         phi[t] = make_float2(o.x + kHalfLn2 * pr, o.y + pi);
@@ -112,8 +135,9 @@ __global__ __launch_bounds__(256) void p2p_kernel(const float2 *__restrict__ xy,
   }
 }
 
-// P2P^T with the same layout: one wave per source leaf, lanes split into
-// NSG sources x NPH target phases over the 3x3 neighbour leaves.  For the
+// P2P^T with the same layout: one wave per source leaf, sources in chunks of
+// up to 64, each chunk's lanes split into sources x target phases over the
+// 3x3 neighbour leaves.  For the
 // pair r = z_t - z_s and cotangents (c, e) of (phi, field) at target t:
 //   dq_s += Re(c log r) + Re(e / r),   G_s += q_s (-c / r + e / r^2),
 // G_s being conj of the position gradient packed as dRe + i dIm.
@@ -143,23 +167,22 @@ __global__ __launch_bounds__(256) void p2p_backward_kernel(const float2 *__restr
     tb[d] = in ? tls[tm] : 0;
     te[d] = in ? tls[tm + 1] : 0;
   }
-  int nsg = 1;
-  while (nsg < ns && nsg < 64) nsg <<= 1;
-  const int nph = 64 / nsg;
-  const int si = lane & (nsg - 1), ph = lane / nsg;
   constexpr float kHalfLn2 = 0.346573590279972654709f;  // log(r2) / 2 = kHalfLn2 log2(r2)
-  for (int32_t c0 = 0; c0 < ns; c0 += nsg) {
-    const int32_t sidx = s0 + c0 + si;
-    const bool act = c0 + si < ns;
-    const float2 zs = xy[act ? sidx : s0];
+  for (int32_t c0 = 0; c0 < ns; c0 += 64) {
+    const ChunkLanes cl(ns - c0 < 64 ? ns - c0 : 64, lane);
+    const int32_t sidx = s0 + c0 + cl.i;
+    const bool act = cl.active();
+    const int ph = act ? cl.ph : 0, nph = cl.nph;
+    const float2 zs = xy[sidx];
     float alog = 0.f, aang = 0.f, aq = 0.f, gr = 0.f, gi = 0.f;
 #pragma unroll
     for (int d = 0; d < 9; ++d) {
-      for (int32_t t = tb[d] + ph; t < te[d]; t += nph) {
+      for (int32_t t = act ? tb[d] + ph : te[d]; t < te[d]; t += nph) {
         const float2 z = txy[t];
         const float rx = z.x - zs.x, ry = z.y - zs.y;
         const float r2 = fmaf(rx, rx, ry * ry);
-        const bool self = r2 == 0.f;  // coincident pair: skipped
+        // own leaf: a coincident pair is skipped
+        const bool self = d == 4 && r2 == 0.f;
         const float r2s = self ? 1.f : r2;
         const float inv = __builtin_amdgcn_rcpf(r2s);
         const float ir = rx * inv, ii = -ry * inv;  // 1/r
@@ -181,16 +204,16 @@ __global__ __launch_bounds__(256) void p2p_backward_kernel(const float2 *__restr
         }
       }
     }
-    for (int m = nsg; m < 64; m <<= 1) {  // combine the phases: lane ph = 0 ends with the total
+    if (nph > 1) {  // combine the phases: lane ph = 0 ends with the total
       if (CPHI) {
-        alog += __shfl_xor(alog, m);
-        aang += __shfl_xor(aang, m);
+        alog = phase_sum(alog, cl, lane);
+        aang = phase_sum(aang, cl, lane);
       }
-      if (CF) aq += __shfl_xor(aq, m);
-      gr += __shfl_xor(gr, m);
-      gi += __shfl_xor(gi, m);
+      if (CF) aq = phase_sum(aq, cl, lane);
+      gr = phase_sum(gr, cl, lane);
+      gi = phase_sum(gi, cl, lane);
     }
-    if (act && ph == 0) {
+    if (act && cl.ph == 0) {
       const float qs = q[sidx];
       gq[sidx] += fmaf(kHalfLn2, alog, aq) - aang;
       const float2 o = G[sidx];

@@ -109,6 +109,53 @@ def test_p2p_matches_oracle(P):
     assert rel(f.cpu().numpy(), fr) < 1e-5
 
 
+def _leaf_points(counts, depth, seed):
+    """Points with exactly counts[m] of them in the leaf of Morton index m,
+    placed away from the leaf's edges."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    side = 1 << depth
+    out = []
+    for m, c in enumerate(counts):
+        ix = sum(((m >> (2 * b)) & 1) << b for b in range(depth))
+        iy = sum(((m >> (2 * b + 1)) & 1) << b for b in range(depth))
+        u = rng.uniform(0.05, 0.95, size=(c, 2))
+        out.append(np.stack([(ix + u[:, 0]) / side, (iy + u[:, 1]) / side], axis=1))
+    return np.concatenate(out).astype(np.float32)
+
+
+def test_p2p_leaf_sizes_match_oracle(P):
+    """Forward and transpose near field with leaves of exactly the sizes where
+    the lane split of a chunk changes (1, 2, 3, 5, 31..33, 63..65, 128, 129),
+    empty leaves, and targets that coincide with sources."""
+    import torch
+    depth = 3
+    sizes = [0, 1, 2, 3, 5, 7, 16, 17, 31, 32, 33, 63, 64, 65, 100, 128, 129]
+    rng = np.random.Generator(np.random.PCG64(5))
+    scount = [sizes[i % len(sizes)] for i in range(64)]
+    tcount = list(rng.permutation(scount))
+    xy = _leaf_points(scount, depth, 6)
+    t = np.concatenate([_leaf_points(tcount, depth, 7), xy[::97]])  # some coincide with sources
+    q = sy.charges(len(xy), 8)
+    perm, ls = P.build_tree(_t(xy), depth)
+    tp, tls = P.build_tree(_t(t), depth)
+    xs, qs, ts = P.gather(_t(xy), perm), P.gather(_t(q), perm), P.gather(_t(t), tp)
+    phi, f = P.p2p(xs, qs, ls, ts, tls, depth)
+    pr, lr = oracle.build_tree(xy.astype(np.float64), depth)
+    tpr, tlr = oracle.build_tree(t.astype(np.float64), depth)
+    X, Q, T = xy[pr].astype(np.float64), q[pr].astype(np.float64), t[tpr].astype(np.float64)
+    phir, fr = oracle.p2p(X, Q, lr, T, tlr, depth)
+    assert rel(phi.cpu().numpy().real, phir.real) < 1e-5
+    assert rel(f.cpu().numpy(), fr) < 1e-5
+    c = (rng.standard_normal(len(t)) + 1j * rng.standard_normal(len(t))).astype(np.complex64)
+    e = (rng.standard_normal(len(t)) + 1j * rng.standard_normal(len(t))).astype(np.complex64)
+    gq = torch.zeros(len(xy), dtype=torch.float32, device="cuda")
+    G = torch.zeros(len(xy), dtype=torch.complex64, device="cuda")
+    P.p2p_backward(xs, qs, ls, ts, tls, depth, _t(c), _t(e), gq, G)
+    gqr, Gr = oracle.p2p_transpose(X, Q, lr, T, tlr, depth, c.astype(np.complex128), e.astype(np.complex128))
+    assert rel(gq.cpu().numpy(), gqr) < 1e-5
+    assert rel(G.cpu().numpy(), Gr) < 1e-5
+
+
 # ---------------------------------------------------------- pipeline ---
 
 @pytest.mark.parametrize("n,depth,p,kind", [(4096, 4, 8, "uniform"), (4096, 4, 12, "uniform"),

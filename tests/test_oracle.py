@@ -86,6 +86,24 @@ def test_operator_identities(p):
         assert np.allclose(A, left[:, None] * B * right[None, :], rtol=1e-12, atol=0)
 
 
+@pytest.mark.parametrize("p", [8, 12, 20])
+def test_symmetric_offset_identities(p):
+    """The negative of an offset shares the scalings of the offset itself:
+    A(-d) = D1(d) B' D2(d) with B'_nk = -(-1)^(n+k) C(n+k, k), and the log row
+    r(-d)_k = (-1)^k r(d)_k for k >= 1, r(-d)_0 = r(d)_0 +- i pi."""
+    from math import comb, pi
+    for d in [2.0 + 0j, -2.0 + 1.0j, 1.0 - 2.0j, -2.0 - 2.0j, 0.0 + 2.0j]:
+        Am = oracle.m2l_operator(-d, p)
+        n = np.arange(p)
+        Bp = np.array([[-((-1) ** (a + k)) * comb(a + k, k) for k in range(p)] for a in range(p)], np.float64)
+        left = ((-1.0) ** n) * d ** (-(n + 1))
+        right = d ** (-n.astype(np.float64))
+        assert np.allclose(Am, left[:, None] * Bp * right[None, :], rtol=1e-12, atol=0)
+        r, rm = oracle.log_row(d, p), oracle.log_row(-d, p)
+        assert np.allclose(rm[1:], ((-1.0) ** n[1:]) * r[1:], rtol=1e-13, atol=0)
+        assert np.isclose(abs(rm[0] - r[0]), pi, rtol=1e-14) and abs((rm[0] - r[0]).real) < 1e-14
+
+
 def test_single_pair_p2m_m2l_l2p_vs_direct():
     """One source box, one well-separated target box: P2M -> M2L -> L2P
     reproduces the direct Cauchy and log sums to the truncation error."""
