@@ -3,9 +3,10 @@
 //   b(t) = sum_{o in O_c(t)} [ r_o . M~(t + o) + log(h) M~_0(t + o) ],
 // the constant term the complex logarithm adds to Eq. (eq:M2Lmat)'s local
 // expansion.  One workgroup per 8x8 target tile stages the 12x12 source block
-// and the 40 log rows in LDS; four lanes share a target box, each summing a
-// quarter of the k range over the box's 27 offsets, then reduce with lane
-// shuffles.  Vector-ALU work of 1/p of the M2L itself.
+// and the 49 log-row slots in LDS as float4 chunks (two coefficients each);
+// four lanes share a target box, each summing a quarter of the k range over
+// the box's 27 offsets with float4 reads, then reduce with lane shuffles.
+// Vector-ALU work of 1/p of the M2L itself.
 #include "fmm2d_internal.h"
 #include "m2l_bank.h"
 #include "m2l_common.h"
@@ -15,9 +16,11 @@ namespace fmm2d {
 template <int P>
 __global__ __launch_bounds__(256) void m2l_logrow_fwd_kernel(const float2 *__restrict__ X, float2 *__restrict__ bout,
                                                              const float2 *__restrict__ rsrc, TileMap map) {
-  constexpr int Q = P / 4;  // k values per lane
-  __shared__ float2 lx[kRegBoxes][P];
-  __shared__ float2 lr[kSlots][P];
+  constexpr int C4 = P / 2;   // float4 chunks of a box record
+  constexpr int CL = C4 / 4;  // chunks per lane: a quarter of the k range
+  constexpr int kStride = C4 + 1;  // padded box stride: boxes read together spread over the banks
+  __shared__ float4 lx[kRegBoxes * kStride];
+  __shared__ float4 lr[kSlots * C4];
   const int tid = threadIdx.x;
 
   int level, tile;
@@ -28,13 +31,15 @@ __global__ __launch_bounds__(256) void m2l_logrow_fwd_kernel(const float2 *__res
   const int X0 = int(tX) * kTile, Y0 = int(tY) * kTile;
   const int64_t off = level_off(level);
 
-  for (int i = tid; i < kSlots * P; i += 256) lr[i / P][i % P] = rsrc[i];
-  for (int i = tid; i < kRegBoxes * P; i += 256) {
-    const int rb = i / P, k = i - rb * P;
+  const float4 *r4 = reinterpret_cast<const float4 *>(rsrc);
+  for (int e = tid; e < kSlots * C4; e += 256) lr[e] = r4[e];
+  for (int e = tid; e < kRegBoxes * C4; e += 256) {
+    const int rb = e / C4, c = e % C4;
     const int gx = X0 - kHalo + rb % kReg, gy = Y0 - kHalo + rb / kReg;
-    float2 v = make_float2(0.f, 0.f);
-    if (gx >= 0 && gy >= 0 && gx < nside && gy < nside) v = X[(off + morton2(gx, gy)) * P + k];
-    lx[rb][k] = v;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (gx >= 0 && gy >= 0 && gx < nside && gy < nside)
+      v = reinterpret_cast<const float4 *>(X + (off + morton2(uint32_t(gx), uint32_t(gy))) * P)[c];
+    lx[rb * kStride + c] = v;
   }
   __syncthreads();
 
@@ -42,19 +47,22 @@ __global__ __launch_bounds__(256) void m2l_logrow_fwd_kernel(const float2 *__res
   const int tx = box & 7, ty = box >> 3;
   const int sx = 1 - 2 * (tx & 1), sy = 1 - 2 * (ty & 1);
   float br = 0.f, bi = 0.f, s0r = 0.f, s0i = 0.f;
+#pragma unroll 3
   for (int q = 0; q < 27; ++q) {
     const int ox = sx * kOff00.ox[q], oy = sy * kOff00.oy[q];
     const int rb = (ty + kHalo + oy) * kReg + (tx + kHalo + ox);
-    const float2 *r = lr[slot_of(ox, oy)];
+    const float4 *m4 = lx + rb * kStride + g * CL;
+    const float4 *v4 = lr + slot_of(ox, oy) * C4 + g * CL;
 #pragma unroll
-    for (int e = 0; e < Q; ++e) {
-      const int k = g * Q + e;
-      const float2 m = lx[rb][k], rv = r[k];
-      br += rv.x * m.x - rv.y * m.y;
-      bi += rv.x * m.y + rv.y * m.x;
+    for (int h = 0; h < CL; ++h) {
+      const float4 m = m4[h], rv = v4[h];
+      br += rv.x * m.x - rv.y * m.y + rv.z * m.z - rv.w * m.w;
+      bi += rv.x * m.y + rv.y * m.x + rv.z * m.w + rv.w * m.z;
+      if (h == 0) {  // k = 0 for lane g = 0, the only lane whose sum is used
+        s0r += m.x;
+        s0i += m.y;
+      }
     }
-    s0r += lx[rb][0].x;
-    s0i += lx[rb][0].y;
   }
   br += __shfl_xor(br, 1);
   bi += __shfl_xor(bi, 1);
