@@ -191,14 +191,6 @@ __global__ void pascal_bank_kernel(float *bank) {
       const cd d = pascal_d(dir, cls, q);
       const cd w = log_row_entry(d.re, d.im, 0);
       v = ri ? w.im : w.re;
-    } else if (i >= B::r_off && i < B::r_off + B::r_floats) {
-      const size_t e = i - B::r_off;
-      const int ri = int(e % 2), k = int((e / 2) % P), slot = int(e / 2 / P);
-      int ox, oy;
-      if (slot_used(slot, ox, oy)) {
-        const cd rv = log_row_entry(double(-ox), double(-oy), k);
-        v = ri ? rv.im : rv.re;
-      }
     }
     bank[i] = float(v);
   }

@@ -24,8 +24,8 @@
 // so a pair costs the two products of its offsets but one D1 accumulation.
 //
 // The log row b rides in rows p .. p+3 of the product when p is not a
-// multiple of 16 (m2l_pascal_bank.h); for p = 16 it is computed by
-// m2l_logrow.hip.  The adjoint applies A~(d)^T = D2(d) B D1(d) over the
+// multiple of 16 (m2l_pascal_bank.h); for p = 16 the loop forms it on the
+// vector ALU from the D2-scaled sources it already holds.  The adjoint applies A~(d)^T = D2(d) B D1(d) over the
 // class's own list with d = +o, and adds the log row's transpose per offset
 // on the VALU: gM~_k += d^-k (Y_k - gb / k) for k >= 1 and
 // gM~_0 += Y_0 + (log d + log h) gb.
@@ -66,8 +66,8 @@ struct LdsPascal {
   float4 tab[4 * (PascalTab<P>::kIn4 + PascalTab<P>::kOut4)];
 };
 
-template <int P>
-constexpr int kPascalWgPerCu = P <= 16 ? 3 : 2;
+template <int P, bool WB = false>
+constexpr int kPascalWgPerCu = P <= 16 && !WB ? 3 : 2;  // WB: the in-loop log row's registers
 
 // Symmetric offsets taken in pairs (m2l_pascal_bank.h).  A pair holds two
 // staged sources and B' in registers; the adjoints for p = 16 and 20 have no
@@ -232,7 +232,12 @@ __device__ __forceinline__ void fetch_store(const Fetched<P, W, ADJ> &f, float *
 template <int P>
 constexpr int kTabPer = (4 * (PascalTab<P>::kIn4 + PascalTab<P>::kOut4) + kPThreads - 1) / kPThreads;
 
-template <int P, bool ADJ, int CX, int CY>
+// WB: the forward's log row b formed in the loop, for orders whose MFMA
+// tiles have no spare rows (p = 16): from the D2-scaled sources each lane
+// already holds, b gets -1/k (a pair's second offset: -(-1)^k / k) times
+// scaled coefficient k >= 1, log d times coefficient 0, and log h times the
+// sum of coefficient 0.
+template <int P, bool ADJ, int CX, int CY, bool WB>
 __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *__restrict__ X,
                                            const float2 *__restrict__ gbin, float2 *__restrict__ Y,
                                            float2 *__restrict__ bout, const float *__restrict__ bank,
@@ -263,6 +268,18 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
 
   // adjoint: -1/k for this lane's output rows k = 16 mt + 4 kk + r (k = 0: the
   // log d + log h term is added per offset; rows >= p: zero)
+  // WB: this lane's log-row weights -1/k, k = S kk + s.  S is even, so the
+  // parity of k is that of s, and a pair's second offset takes the same
+  // weights with the sign of (-1)^s.
+  static_assert(!WB || S % 2 == 0, "in-loop log row: p a multiple of 8");
+  float wb1[WB ? S : 1];
+  if constexpr (WB) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int k = S * kk + s;
+      wb1[s] = k >= 1 ? -1.f / float(k) : 0.f;
+    }
+  }
   float cm[ADJ ? MT : 1][4], cm2[ADJ ? MT : 1][4];  // cm2: the negative offset's, -(-1)^k / k
   if (ADJ) {
 #pragma unroll
@@ -426,6 +443,9 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
       }
     };
 
+    // WB: the log row's parts: the k >= 1 sum, and (log d + log h) times
+    // coefficient 0, used by the lanes that hold k = 0
+    float lbr = 0.f, lbi = 0.f, c0r = 0.f, c0i = 0.f;
     load_x(xc, ST.q1[0]);
     if (ST.q2[0] >= 0) load_x(xc2, ST.q2[0]);
     load_in(ic, ST.q1[0]);
@@ -474,6 +494,27 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
         pim[j & 1][mt] = b;
       }
       if (j > 0) accumulate(pr[(j - 1) & 1], pim[(j - 1) & 1], oc, gbc, lgc, ST.q2[j > 0 ? j - 1 : 0] >= 0);
+      if constexpr (WB) {  // this step's log-row terms, from the sources its products read
+        const float lr1 = lgt[2 * q1] + logh, li1 = lgt[2 * q1 + 1];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          lbr = fmaf(wb1[s], sr[s], lbr);
+          lbi = fmaf(wb1[s], si[s], lbi);
+        }
+        c0r = fmaf(lr1, sr[0], fmaf(-li1, si[0], c0r));
+        c0i = fmaf(lr1, si[0], fmaf(li1, sr[0], c0i));
+        if (pair) {
+          const float lr2 = lgt[2 * q2] + logh, li2 = lgt[2 * q2 + 1];
+#pragma unroll
+          for (int s = 0; s < S; ++s) {
+            const float w = (s & 1) ? -wb1[s] : wb1[s];
+            lbr = fmaf(w, sr2[s], lbr);
+            lbi = fmaf(w, si2[s], lbi);
+          }
+          c0r = fmaf(lr2, sr2[0], fmaf(-li2, si2[0], c0r));
+          c0i = fmaf(lr2, si2[0], fmaf(li2, sr2[0], c0i));
+        }
+      }
       // the next step's operands, under this step's products
       if (j + 1 < NST) {
         scale(xn, in_, sr, si);
@@ -495,6 +536,7 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
       // and their scalings live.  Opaque per step, they are formed here.
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) asm volatile("" : "+v"(accr[mt]), "+v"(acci[mt]));
+      if constexpr (WB) asm volatile("" : "+v"(lbr), "+v"(lbi), "+v"(c0r), "+v"(c0i));
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -507,6 +549,13 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
     const int gx = geo.X0 + tx, gy = geo.Y0 + ty;
     const bool valid = gx < geo.nside && gy < geo.nside;
     const int64_t gbox = geo.off + morton2(uint32_t(gx), uint32_t(gy));
+    if constexpr (WB) {  // the four lane groups of box j hold its k ranges
+      lbr += __shfl_xor(lbr, 16);
+      lbi += __shfl_xor(lbi, 16);
+      lbr += __shfl_xor(lbr, 32);
+      lbi += __shfl_xor(lbi, 32);
+      if (valid && kk == 0) bout[gbox] = make_float2(lbr + c0r, lbi + c0i);
+    }
     if (valid) {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
@@ -538,8 +587,8 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
   }
 }
 
-template <int P, bool ADJ>
-__global__ __launch_bounds__(kPThreads, kPascalWgPerCu<P>) void m2l_pascal_kernel(const float2 *__restrict__ X,
+template <int P, bool ADJ, bool WB>
+__global__ __launch_bounds__(kPThreads, (kPascalWgPerCu<P, WB>)) void m2l_pascal_kernel(const float2 *__restrict__ X,
                                                                   const float2 *__restrict__ gbin,
                                                                   float2 *__restrict__ Y, float2 *__restrict__ bout,
                                                                   const float *__restrict__ bank, TileMap map,
@@ -563,26 +612,31 @@ __global__ __launch_bounds__(kPThreads, kPascalWgPerCu<P>) void m2l_pascal_kerne
   }
   // every branch executes the same sequence of barriers; the branch is uniform per wave
   switch (wave) {
-    case 0: pascal_run<P, ADJ, 0, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid, tv); break;
-    case 1: pascal_run<P, ADJ, 1, 0>(sm, X, gbin, Y, bout, bank, map, ntiles, tid, tv); break;
-    case 2: pascal_run<P, ADJ, 0, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid, tv); break;
-    default: pascal_run<P, ADJ, 1, 1>(sm, X, gbin, Y, bout, bank, map, ntiles, tid, tv); break;
+    case 0: pascal_run<P, ADJ, 0, 0, WB>(sm, X, gbin, Y, bout, bank, map, ntiles, tid, tv); break;
+    case 1: pascal_run<P, ADJ, 1, 0, WB>(sm, X, gbin, Y, bout, bank, map, ntiles, tid, tv); break;
+    case 2: pascal_run<P, ADJ, 0, 1, WB>(sm, X, gbin, Y, bout, bank, map, ntiles, tid, tv); break;
+    default: pascal_run<P, ADJ, 1, 1, WB>(sm, X, gbin, Y, bout, bank, map, ntiles, tid, tv); break;
   }
 }
 
 template <int P>
 void launch_pascal_p(const float *M, const float *gb_in, float *L, float *b, const TileMap &map, int ntiles,
                      bool adjoint, const void *ops, hipStream_t s) {
-  const int slots = kPascalWgPerCu<P> * num_cus();
+  constexpr bool kWB = !PascalCfg<P>::kLogInRows;  // the in-loop log row exists for this order
+  const bool wb = kWB && !adjoint && b;              // no spare rows: b formed in the loop
+  const int slots = (wb ? kPascalWgPerCu<P, kWB> : kPascalWgPerCu<P>) * num_cus();
   const int grid = ntiles < slots ? ntiles : slots;
   const float2 *X = reinterpret_cast<const float2 *>(M);
   float2 *Y = reinterpret_cast<float2 *>(L);
   const float *bank = static_cast<const float *>(ops);
   if (adjoint)
-    hipLaunchKernelGGL((m2l_pascal_kernel<P, true>), dim3(grid), dim3(kPThreads), 0, s, X,
+    hipLaunchKernelGGL((m2l_pascal_kernel<P, true, false>), dim3(grid), dim3(kPThreads), 0, s, X,
                        reinterpret_cast<const float2 *>(gb_in), Y, nullptr, bank, map, ntiles);
+  else if (wb)
+    hipLaunchKernelGGL((m2l_pascal_kernel<P, false, kWB>), dim3(grid), dim3(kPThreads), 0, s, X, nullptr, Y,
+                       reinterpret_cast<float2 *>(b), bank, map, ntiles);
   else
-    hipLaunchKernelGGL((m2l_pascal_kernel<P, false>), dim3(grid), dim3(kPThreads), 0, s, X, nullptr, Y,
+    hipLaunchKernelGGL((m2l_pascal_kernel<P, false, false>), dim3(grid), dim3(kPThreads), 0, s, X, nullptr, Y,
                        reinterpret_cast<float2 *>(b), bank, map, ntiles);
 }
 
@@ -599,10 +653,7 @@ int launch_m2l_pascal(const float *M, const float *gb_in, float *L, float *b, in
     case 16: launch_pascal_p<16>(M, gb_in, L, b, map, ntiles, adjoint, ops, s); break;
     case 20: launch_pascal_p<20>(M, gb_in, L, b, map, ntiles, adjoint, ops, s); break;
   }
-  int rc = check_launch(adjoint ? "m2l_backward (f32, Pascal form)" : "m2l (f32, Pascal form)");
-  if (rc == FMM2D_OK && !adjoint && b && (p % 16) == 0)  // no spare rows: separate log-row pass
-    rc = launch_m2l_logrow_fwd(M, b, p, lmin, lmax, static_cast<const float *>(ops) + PascalBank<16>::r_off, s);
-  return rc;
+  return check_launch(adjoint ? "m2l_backward (f32, Pascal form)" : "m2l (f32, Pascal form)");
 }
 
 }  // namespace fmm2d

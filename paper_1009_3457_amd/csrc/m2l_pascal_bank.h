@@ -31,7 +31,7 @@
 // p+1 = p+2 = p+3 = e_0.  Output scalings 1, log d, 1 and, for a pair,
 // log(-d) - log d (= +-i pi; 0 for a single offset), so that
 //     b = L[p] + L[p+1] + L[p+3] + log(h) L[p+2].
-// For p = 16 the separate b pass reads section r (the forward log rows).
+// For p = 16 (no spare rows) the kernel forms b from the D2-scaled sources.
 #pragma once
 
 #include <cstddef>
@@ -56,7 +56,6 @@ struct PascalCfg {
 //   tin  [dir][cls][q][kk][LI]             forward: d^-k;        adjoint: (-1)^k d^-(k+1)
 //   tout [dir][cls][q][mt][kk][LO]         forward: D1 and the log rows; adjoint: d^-n (rows < p)
 //   lg   [dir][cls][q][2]                  log d
-//   r    [slot][P][2]                      forward log row r_o (separate b pass, p = 16)
 //   zero [64][P][2]                        zeros: the source record of a box outside
 //                                          the level, for any box position in an 8x8 block
 // dir 0 is the forward translation (d = -o for source t + o of class cls,
@@ -70,15 +69,13 @@ struct PascalBank {
   static constexpr size_t tin_floats = size_t(2) * 4 * 27 * 4 * C::LI;
   static constexpr size_t tout_floats = size_t(2) * 4 * 27 * C::MT * 4 * C::LO;
   static constexpr size_t lg_floats = size_t(2) * 4 * 27 * 2;
-  static constexpr size_t r_floats = size_t(kSlots) * P * 2;
   static constexpr size_t zero_floats = size_t(64) * P * 2;
   static constexpr size_t bf_off = 0;
   static constexpr size_t bfp_off = (bf_off + bf_floats + 63) / 64 * 64;
   static constexpr size_t tin_off = (bfp_off + bfp_floats + 63) / 64 * 64;
   static constexpr size_t tout_off = (tin_off + tin_floats + 63) / 64 * 64;
   static constexpr size_t lg_off = (tout_off + tout_floats + 63) / 64 * 64;
-  static constexpr size_t r_off = (lg_off + lg_floats + 63) / 64 * 64;
-  static constexpr size_t zero_off = (r_off + r_floats + 63) / 64 * 64;
+  static constexpr size_t zero_off = (lg_off + lg_floats + 63) / 64 * 64;
   static constexpr size_t total_floats = (zero_off + zero_floats + 63) / 64 * 64;
   __host__ __device__ static constexpr size_t tin_rec(int dir, int cls, int q) {
     return tin_off + ((size_t(dir) * 4 + cls) * 27 + q) * 4 * C::LI;
