@@ -48,8 +48,8 @@ if ROOT not in sys.path:
 # M2L of Eq. (eq:M2Lmat); at p = 16 b needs a separate pass)
 WORKLOADS = {
     "m2l_uniform_n1M_d8_p12": (1 << 20, 8, 12, "uniform", "f32_pascal", "Lb"),
-    "m2l_mixed_n4M_d9_p16": (1 << 22, 9, 16, "mixed", "f32", "L"),
-    "m2l_mixed_n16M_d10_p20": (1 << 24, 10, 20, "mixed", "f32", "L"),
+    "m2l_mixed_n4M_d9_p16": (1 << 22, 9, 16, "mixed", "f32_pascal", "L"),
+    "m2l_mixed_n16M_d10_p20": (1 << 24, 10, 20, "mixed", "f32_pascal", "L"),
     "m2l_uniform_n4k_d4_p8": (4096, 4, 8, "uniform", "f32", "Lb"),
 }
 DEFAULT = "m2l_uniform_n1M_d8_p12"
