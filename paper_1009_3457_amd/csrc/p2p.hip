@@ -186,22 +186,26 @@ __global__ __launch_bounds__(256) void p2p_backward_kernel(const float2 *__restr
         const float r2s = self ? 1.f : r2;
         const float inv = __builtin_amdgcn_rcpf(r2s);
         const float ir = rx * inv, ii = -ry * inv;  // 1/r
+        // G_s gathers (-c + e / r) / r: w = -c + e / r, then w times 1/r
+        float wr = 0.f, wi = 0.f;
         if (CPHI) {
           const float2 c0v = cphi[t];
           const float cx = self ? 0.f : c0v.x, cy = self ? 0.f : c0v.y;
           alog = fmaf(cx, __builtin_amdgcn_logf(r2s), alog);  // hardware log2
           aang = fmaf(cy, atan2_p2p(ry, self ? 1.f : rx), aang);
-          gr -= cx * ir - cy * ii;
-          gi -= cx * ii + cy * ir;
+          wr = -cx;
+          wi = -cy;
         }
         if (CF) {
           const float2 e0 = cfield[t];
           const float ex = self ? 0.f : e0.x, ey = self ? 0.f : e0.y;
-          aq += ex * ir - ey * ii;
-          const float i2r = ir * ir - ii * ii, i2i = 2.f * ir * ii;  // 1/r^2
-          gr += ex * i2r - ey * i2i;
-          gi += ex * i2i + ey * i2r;
+          const float ur = fmaf(ex, ir, -ey * ii), ui = fmaf(ex, ii, ey * ir);  // e / r
+          aq += ur;
+          wr += ur;
+          wi += ui;
         }
+        gr = fmaf(wr, ir, fmaf(-wi, ii, gr));
+        gi = fmaf(wr, ii, fmaf(wi, ir, gi));
       }
     }
     if (nph > 1) {  // combine the phases: lane ph = 0 ends with the total
