@@ -57,8 +57,9 @@ def test_pascal_matches_oracle_every_level(P, p, depth):
         assert rel(b[sl], br[sl]) < TOL, (l, rel(b[sl], br[sl]))
 
 
-def test_pascal_level_range_leaves_other_levels_untouched(P):
-    depth, p = 5, 12
+@pytest.mark.parametrize("p", [12, 16])  # b in spare MFMA rows; b formed in the loop
+def test_pascal_level_range_leaves_other_levels_untouched(P, p):
+    depth = 5
     Ms32, M_exact = multipoles(depth, p, 4 ** depth * 10, seed=3)
     L, b = _run(P, Ms32, depth, p, lmin=3, lmax=4, sentinel=7.0)
     Lr, br = oracle.m2l(M_exact, depth, p, 3, 4)
