@@ -80,6 +80,8 @@ def _load():
         lib.ora_m2l.argtypes = [_dp, _dp, _dp, _int, _int, _int, _int]
         lib.ora_m2l_boxes.argtypes = [_dp, _int, _int, _i64p, _i64, _dp, _dp]
         lib.ora_m2l_transpose.argtypes = [_dp, _dp, _dp, _int, _int, _int, _int]
+        lib.ora_m2l_transpose_boxes.argtypes = [_dp, _dp, _int, _int, _i64p, _i64, _dp]
+        lib.ora_set_num_threads.argtypes = [_int]
         lib.ora_l2l.argtypes = [_dp, _dp, _dp, _dp, _int, _int]
         lib.ora_l2l_transpose.argtypes = [_dp, _dp, _int, _int]
         lib.ora_m2m_transpose.argtypes = [_dp, _int, _int]
@@ -131,6 +133,11 @@ def _c128(a):
 def num_threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(_load().ora_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Sets the OpenMP threads of the oracle's parallel loops."""
+    _load().ora_set_num_threads(int(n))
 
 
 def num_boxes(depth: int) -> int:
@@ -219,6 +226,17 @@ def m2l_transpose(gL, gb, depth: int, p: int, lmin: int = 2, lmax: int | None = 
     gM = np.zeros((num_boxes(depth), p), np.complex128)
     _load().ora_m2l_transpose(_d(_c128(gL)), _d(None if gb is None else _c128(gb)), _d(gM),
                               depth, p, lmin, lmax)
+    return gM
+
+
+def m2l_transpose_boxes(gL_level, gb_level, level: int, p: int, boxes):
+    """The transpose of m2l for selected source boxes (Morton indices) of one
+    level, gathered over each source's own interaction list; returns gM
+    [len(boxes), p]."""
+    boxes = np.ascontiguousarray(boxes, dtype=np.int64)
+    gM = np.zeros((boxes.size, p), np.complex128)
+    _load().ora_m2l_transpose_boxes(_d(_c128(gL_level)), _d(None if gb_level is None else _c128(gb_level)),
+                                    level, p, boxes.ctypes.data_as(_i64p), boxes.size, _d(gM))
     return gM
 
 

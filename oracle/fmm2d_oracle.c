@@ -375,6 +375,52 @@ void ora_m2l_transpose(const cplx *gL, const cplx *gb, cplx *gM, int depth, int 
 }
 
 /*
+ * The same transpose for a sample of source boxes of one level, written as a
+ * gather over each source's own interaction list.  The list is symmetric at a
+ * level (s is in IL(t) exactly when t is in IL(s)), so
+ *   gM_k(s) = sum_{t in IL(s)} [ sum_n A(c_t - c_s)_{nk} gL_n(t) + r_k(c_t - c_s) gb(t) ],
+ * with the operator built for d = c_t - c_s exactly as in the forward map.
+ * gLlev, gblev point at the level's cotangents (gblev may be NULL); gMout is
+ * [nb][p], overwritten.
+ */
+void ora_m2l_transpose_boxes(const cplx *gLlev, const cplx *gblev, int l, int p,
+                             const int64_t *boxes, int64_t nb, cplx *gMout)
+{
+    binom_init();
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t e = 0; e < nb; ++e) {
+        int64_t s = boxes[e], sx, sy, list[32];
+        ora_demorton(s, l, &sx, &sy);
+        cplx cs = box_centre(sx, sy, l);
+        int cnt = ora_interaction_list(l, sx, sy, list);
+        cplx A[ORA_MAXP * ORA_MAXP], r[ORA_MAXP];
+        cplx *g = gMout + e * p;
+        for (int k = 0; k < p; ++k) g[k] = 0.0;
+        for (int j = 0; j < cnt; ++j) {
+            int64_t t = list[j];
+            cplx d = box_centre_m(t, l) - cs;
+            ora_m2l_operator(creal(d), cimag(d), p, A);
+            for (int k = 0; k < p; ++k)
+                for (int n = 0; n < p; ++n) g[k] += A[n * p + k] * gLlev[t * p + n];
+            if (gblev) {
+                ora_log_row(creal(d), cimag(d), p, r);
+                for (int k = 0; k < p; ++k) g[k] += r[k] * gblev[t];
+            }
+        }
+    }
+}
+
+/* Sets the number of threads the parallel loops use (no-op without OpenMP). */
+void ora_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/*
  * L2L (downward sweep, "aggregation of LEs"; textbook exact re-expansion of a
  * truncated polynomial), delta = c_child - c_parent:
  *   L_n(child) += sum_{m>=n} C(m,n) delta^(m-n) L_m(parent)

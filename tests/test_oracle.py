@@ -313,6 +313,80 @@ def test_scaled_basis_roundtrip_is_exact():
     assert np.array_equal(oracle.unscale_locals(oracle.scale_locals(M, depth), depth), M)
 
 
+def test_scale_multipoles_closed_form():
+    """One source q at z: the multipole expansion of the level-l box holding it
+    is M_k = q (z - c_l)^k, so the scaled one must be q ((z - c_l) / h_l)^k with
+    h_l = 2^-l.  The closed form is formed here from the box centre; only
+    P2M, M2M and scale_multipoles come from the oracle.  A wrong exponent sign
+    or power in the helper fails at every level but the root."""
+    depth, p = 6, 12
+    z = 0.3712890625 + 0.6259765625j  # exact in FP32 and FP64
+    q = -0.75
+    xy = np.array([[z.real, z.imag]])
+    perm, ls = oracle.build_tree(xy, depth)
+    M = oracle.m2m(oracle.p2m(xy[perm], np.array([q]), ls, depth, p), depth, p)
+    Ms = oracle.scale_multipoles(M, depth)
+    k = np.arange(p)
+    for l in range(depth + 1):
+        h = 2.0 ** -l
+        ix, iy = int(z.real / h), int(z.imag / h)
+        c = (ix + 0.5) * h + 1j * (iy + 0.5) * h
+        row = Ms[oracle.level_offset(l) + oracle.morton(ix, iy, l)]
+        expect = q * ((z - c) / h) ** k
+        assert np.allclose(row, expect, rtol=1e-12, atol=1e-14), l
+        # every other box of the level is empty
+        lev = Ms[oracle.level_offset(l):oracle.level_offset(l + 1)]
+        assert np.count_nonzero(np.abs(lev).sum(axis=1)) == 1
+
+
+def test_scale_locals_closed_form():
+    """A unit charge at the centre of box s gives, in a box t of its
+    interaction list, L_n = (-1)^n q d^-(n+1) with d = c_t - c_s (the k = 0
+    column of Eq. (eq:M2Lmat)).  Scaled by h^(n+1), that is
+    (-1)^n q delta^-(n+1) with delta = d / h the integer box offset: the same
+    numbers at every level.  The closed form uses only the integer offset."""
+    p, q = 12, 1.5
+    n = np.arange(p)
+    for l in (2, 3, 5):
+        side = 1 << l
+        sx, sy = 1, side - 2
+        for tx, ty in ((sx + 2, sy), (sx + 3, sy - 2), (sx - 1, sy + 1), (sx + 2, sy + 1)):
+            if not (0 <= tx < side and 0 <= ty < side):
+                continue
+            t_m = oracle.morton(tx, ty, l)
+            if oracle.morton(sx, sy, l) not in oracle.interaction_list(l, tx, ty):
+                continue
+            depth = l
+            M = np.zeros((oracle.num_boxes(depth), p), np.complex128)
+            M[oracle.level_offset(l) + oracle.morton(sx, sy, l), 0] = q
+            L, _ = oracle.m2l(M, depth, p, l, l)
+            Ls = oracle.scale_locals(L, depth)
+            delta = complex(tx - sx, ty - sy)
+            expect = (-1.0) ** n * q * delta ** -(n + 1.0)
+            assert np.allclose(Ls[oracle.level_offset(l) + t_m], expect, rtol=1e-13, atol=0), (l, tx, ty)
+            # and unscaled it carries the level's powers of h
+            h = 2.0 ** -l
+            assert np.allclose(L[oracle.level_offset(l) + t_m], expect * h ** -(n + 1.0), rtol=1e-13, atol=0)
+
+
+def test_transpose_gather_equals_scatter():
+    """The sampled transpose (a gather over each source's own list) equals the
+    literal scatter, which the dot-product test pins, at every box of every
+    level, with and without the log row's cotangent."""
+    depth, p = 4, 8
+    g = sy.rng(12)
+    nb = oracle.num_boxes(depth)
+    G = g.standard_normal((nb, p)) + 1j * g.standard_normal((nb, p))
+    gb = g.standard_normal(nb) + 1j * g.standard_normal(nb)
+    for gbv in (gb, None):
+        ref = oracle.m2l_transpose(G, gbv, depth, p)
+        for l in range(2, depth + 1):
+            lo, hi = oracle.level_offset(l), oracle.level_offset(l + 1)
+            boxes = np.arange(hi - lo)
+            got = oracle.m2l_transpose_boxes(G[lo:hi], None if gbv is None else gbv[lo:hi], l, p, boxes)
+            assert np.allclose(got, ref[lo:hi], rtol=1e-12, atol=1e-12), l
+
+
 def test_scaled_operator_is_level_independent():
     """In the scaled basis L~_n = L_n h^(n+1), M~_k = M_k / h^k the M2L matrix
     depends only on the offset in box widths."""
