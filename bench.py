@@ -15,17 +15,26 @@ Prints one JSON line with:
   * translations/s, using the exact, boundary-truncated count;
   * Gop/s, at 8p^2 flops per translation;
   * the roofline of the M2L kernel, timed with HIP events on its stream
-    (mean over the timed launches), at 8p^2 (+8p with b) flops per
-    translation; for the Pascal form also at the 4p^2 + 14p (+4p + 8) flops
-    that form performs ("form");
+    (mean over the timed launches), priced at the flops the launched form
+    performs (Pascal form 4p^2 + 14p, +4p + 8 with b; Gauss form 6p^2 + p,
+    +6p + 2; split precision 24p^2, +24p), and as `effective_frac` at the
+    dense operator's 8p^2 (+8p);
   * launch times one by one after the timed region: warm p10/p50/p90, and
     cold (caches flushed by a 512 MiB fill before each launch) p50;
-  * the adjoint's time;
+  * the adjoint's time and roofline;
+  * the relative error per level against the FP64 oracle's M2L of the same
+    FP32 inputs, for every precision, on the 2^20- and 2^22-point workloads
+    (computed after the timed region, by the oracle run that the CPU baseline
+    times);
   * split precision against FP32: the same step in BF16x3 and FP16x3 on this
     workload and on the 2^22-point, depth-9, p = 16 one;
-  * the FP64 oracle's rate on the host cores;
-  * with --fmm, the time of every stage of the whole FMM and of its reverse
-    pass;
+  * the 2^24-point, depth-10, p = 20 workload: forward and adjoint M2L in
+    every precision, and the whole FMM's forward and reverse stage times;
+  * the gradient of sum (Re phi)^2 at 4096 targets for 2^20 sources (forward
+    plus backward through the whole FMM);
+  * the FP64 oracle's M2L rate on the host cores, at all threads and at one,
+    with the CPU model;
+  * the whole FMM's stage times on the default workload;
   * the fast Gauss transform's Hermite evaluation (Sec. 4.2) at 6,553,600
     targets, p = 12 (or --fgt W): targets/s, its ALU roofline and the FP64
     oracle on a sample.
@@ -57,6 +66,7 @@ MIXED_COMPARE = ["m2l_uniform_n1M_d8_p12", "m2l_mixed_n4M_d9_p16"]
 PEAK_TFLOPS = {"f32": 157.3, "f32_pascal": 157.3, "bf16x3": 2500.0, "f16x3": 2500.0}  # MI355X dense MFMA
 MFMA_FLOPS_FACTOR = {"f32": 1, "f32_pascal": 1, "bf16x3": 3, "f16x3": 3}  # split products per real product
 PEAK_HBM_GBS = 8000.0
+TOLERANCE_VS_FP64 = {"f32": 1e-5, "f32_pascal": 1e-5, "bf16x3": 1e-4, "f16x3": 1e-4}
 PAPER_P12_TRANS_PER_S = 80.05e6  # Tesla C1060, p = 12, depth-8 tree (Table tab:m2ltesla)
 
 # Fast Gauss transform, Hermite evaluation: name -> (depth, p, K).  Sources and
@@ -119,29 +129,58 @@ def _points(kind, n, seed):
     return sy.uniform(n, seed) if kind == "uniform" else sy.mixed(n, seed)
 
 
-def cpu_baseline(Ms_np, depth, p, budget_s=12.0, max_runs=200):
-    """The FP64 oracle's M2L over all levels 2..depth, timed on the host cores.
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, budget_s=12.0, max_runs=200, single_thread=True):
+    """The FP64 oracle's M2L over all levels 2..depth of the workload's own
+    multipole expansions, timed on the host cores.
 
     The oracle builds the operator per translation from Eq. (eq:M2Lmat). The
-    run is repeated while the time budget allows (at least once) and the median
-    is reported."""
+    run is repeated at all threads while the time budget allows (at least
+    once) and the median is reported; with `single_thread` it is also timed
+    once on one thread.  Returns (record, reference): the reference is the
+    oracle's result in the scaled basis the GPU stores, (L~, b or None), from
+    which the per-level errors of the GPU results are computed."""
+    import numpy as np
+
     import oracle
-    M = oracle.unscale_multipoles(Ms_np.astype("complex128"), depth)
+    with_b = w.outputs == "Lb"
+    M = oracle.unscale_multipoles(w.M.cpu().numpy().astype(np.complex128), w.depth)
     times = []
     t_start = time.perf_counter()
     while len(times) < max_runs:
         t0 = time.perf_counter()
-        oracle.m2l(M, depth, p)
+        Lr, br = oracle.m2l(M, w.depth, w.p, with_b=with_b)
         times.append(time.perf_counter() - t0)
         if time.perf_counter() - t_start + times[-1] > budget_s:
             break
-    import paper_1009_3457_amd as P
-    ntrans = P.translation_count(2, depth)
     med = sorted(times)[len(times) // 2]
-    return {"value": ntrans / med, "unit": "translations/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"full M2L, levels 2..{depth}, p={p}, {ntrans} translations, FP64, "
-                      f"median of {len(times)} runs ({med:.3f} s each)"}
+    rec = {"value": w.ntrans / med, "unit": "translations/s", "cores": oracle.num_threads(),
+           "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"full M2L, levels 2..{w.depth}, p={w.p}, {w.ntrans} translations, FP64"
+                     f"{' with b' if with_b else ''}, median of {len(times)} runs ({med:.3f} s each)"}
+    if single_thread:
+        n_all = oracle.num_threads()
+        oracle.set_num_threads(1)
+        try:
+            t0 = time.perf_counter()
+            oracle.m2l(M, w.depth, w.p, with_b=with_b)
+            t1 = time.perf_counter() - t0
+        finally:
+            oracle.set_num_threads(n_all)
+        rec["single_thread"] = {"value": w.ntrans / t1, "unit": "translations/s", "cores": 1,
+                                "sample": f"the same M2L once on one thread ({t1:.3f} s)"}
+    return rec, (oracle.scale_locals(Lr, w.depth), br)
 
 
 class Workload:
@@ -243,80 +282,172 @@ class Workload:
         return {"warm_p10": q(warm, 0.1), "warm_p50": q(warm, 0.5), "warm_p90": q(warm, 0.9),
                 "cold_p50": q(cold, 0.5), "warm_reps": reps, "cold_reps": cold_reps}
 
-    def level_rel_diff(self, ref_L):
-        """max over levels of ||L - ref_L||_F / ||ref_L||_F (device arithmetic)."""
-        import torch
+    def error_vs_fp64(self, ref):
+        """Relative Frobenius error per level of the last launch's L~ (and b)
+        against the FP64 oracle's result `ref` = (L~, b or None) of the same
+        FP32 inputs: {"L": [e_2, ..., e_depth], "b": [...], "max": ...}."""
+        import numpy as np
 
         import paper_1009_3457_amd as P
-        worst = 0.0
+        if ref is None:
+            return None
+        Lr, br = ref
+        L = self.L.cpu().numpy()
+        b = self.b.cpu().numpy() if (self.b is not None and br is not None) else None
+        out = {"levels": list(range(2, self.depth + 1)), "L": [], "b": [] if b is not None else None}
         for l in range(2, self.depth + 1):
-            a, b = P.level_offset(l), P.level_offset(l + 1)
-            den = torch.linalg.vector_norm(ref_L[a:b]).item()
-            num = torch.linalg.vector_norm(self.L[a:b] - ref_L[a:b]).item()
-            worst = max(worst, num / den if den > 0 else num)
-        return worst
+            lo, hi = P.level_offset(l), P.level_offset(l + 1)
+            den = np.linalg.norm(Lr[lo:hi])
+            out["L"].append(float(np.linalg.norm(L[lo:hi] - Lr[lo:hi]) / den) if den > 0 else 0.0)
+            if b is not None:
+                den = np.linalg.norm(br[lo:hi])
+                out["b"].append(float(np.linalg.norm(b[lo:hi] - br[lo:hi]) / den) if den > 0 else 0.0)
+        out["max"] = max(out["L"] + (out["b"] or []))
+        return out
 
 
-def flops_per_translation(p, prec_name, outputs):
-    """Algorithmic flops of one translation: the dense p x p complex mat-vec,
-    8p^2, plus 8p for the log row when b is produced; split precision is
-    priced at its three real products per product (24p^2)."""
-    return (8 * p * p + (8 * p if outputs == "Lb" else 0)) * MFMA_FLOPS_FACTOR[prec_name]
+def dense_flops_per_translation(p, outputs):
+    """The dense operator's count for one translation: the p x p complex
+    mat-vec, 8p^2 (4 multiplies and 4 adds per complex multiply-add), plus 8p
+    for the log row when b is produced."""
+    return 8 * p * p + (8 * p if outputs == "Lb" else 0)
 
 
-def pascal_flops_per_translation(p, outputs):
-    """Flops of one translation as the Pascal form computes it: the scaling by
-    D2 (6p), the two real products with B (4p^2) and the scaled accumulation
-    by D1 (8p), plus 4p + 8 for the log row."""
-    return 4 * p * p + 14 * p + (4 * p + 8 if outputs == "Lb" else 0)
+def own_flops_per_translation(p, prec_name, outputs):
+    """Flops one translation costs in the form that is launched.
+
+    * Pascal form (A~ = D1 B D2): the scaling by D2 (6p), the two real
+      products with B (4p^2) and the scaled accumulation by D1 (8p); the log
+      row adds 4p + 8.
+    * Gauss form: three real p x p products (Ar Xr, Ai Xi, (Ar+Ai)(Xr+Xi)),
+      6p^2, and the p additions forming Xr + Xi; the log row is one more row
+      of the three products (6p) plus the M~_0 sum for the log(h) term (2).
+    * Split precision (BF16x3, FP16x3): three real products with the 2p x 2p
+      real embedding, 24p^2, and 24p for the log row's two real rows."""
+    with_b = outputs == "Lb"
+    if prec_name == "f32_pascal":
+        return 4 * p * p + 14 * p + (4 * p + 8 if with_b else 0)
+    if prec_name == "f32":
+        return 6 * p * p + p + (6 * p + 2 if with_b else 0)
+    return 24 * p * p + (24 * p if with_b else 0)
 
 
 def roofline(w, prec_name, ms):
-    fpt = flops_per_translation(w.p, prec_name, w.outputs)
-    tflops = float(fpt) * w.ntrans / (ms * 1e-3) / 1e12
+    """The M2L kernel against the MFMA peak of its dtype: `achieved` and
+    `frac` at the flops the launched form performs, `effective_frac` at the
+    dense operator's count."""
+    own = own_flops_per_translation(w.p, prec_name, w.outputs)
+    dense = dense_flops_per_translation(w.p, w.outputs)
+    tflops = float(own) * w.ntrans / (ms * 1e-3) / 1e12
+    eff = float(dense) * w.ntrans / (ms * 1e-3) / 1e12
     boxes = sum(4 ** l for l in range(2, w.depth + 1))
     alg_bytes = boxes * w.p * 8 * 2 + (boxes * 8 if w.outputs == "Lb" else 0)
     peak = PEAK_TFLOPS[prec_name]
-    out = {"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s", "frac": tflops / peak,
-           "flops_per_translation": fpt,
-           "traffic": recorded_traffic(w.name, prec_name),
-           "algorithmic_bytes": alg_bytes,
-           "hbm_frac": alg_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
-    if prec_name == "f32_pascal":
-        # the same translations at the arithmetic this form performs: the
-        # dense count above can exceed the peak for it
-        ff = pascal_flops_per_translation(w.p, w.outputs)
-        ft = float(ff) * w.ntrans / (ms * 1e-3) / 1e12
-        out["form"] = {"flops_per_translation": ff, "achieved": ft, "frac": ft / peak}
-    return out
+    return {"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s", "frac": tflops / peak,
+            "flops_per_translation": own,
+            "effective_frac": eff / peak, "dense_flops_per_translation": dense,
+            "traffic": recorded_traffic(w.name, prec_name),
+            "algorithmic_bytes": alg_bytes,
+            "hbm_frac": alg_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
 
 
-def mixed_comparison(seed, dev, steps, warmup, main=None):
+def precision_block(w, prec, steps, warmup, ref, best=None):
+    """One precision on one workload: forward and adjoint time per launch,
+    rooflines, error per level against FP64, and the speedup over `best` =
+    (forward ms, adjoint ms) of the faster FP32 form."""
+    ms, bwd = w.time_m2l(prec, steps, warmup)
+    err = w.error_vs_fp64(ref)
+    rf, rb = roofline(w, prec, ms), roofline(w, prec, bwd)
+    rec = {"ms": ms, "adjoint_ms": bwd, "translations_per_s": w.ntrans / (ms * 1e-3),
+           "roofline_frac": rf["frac"], "effective_frac": rf["effective_frac"],
+           "adjoint_roofline_frac": rb["frac"], "achieved_tflops": rf["achieved"],
+           "error_vs_fp64": err, "tolerance_vs_fp64": TOLERANCE_VS_FP64[prec]}
+    if err is not None:
+        rec["within_tolerance"] = err["max"] <= TOLERANCE_VS_FP64[prec]
+    if best is not None:
+        rec["speedup_vs_f32"] = best[0] / ms
+        rec["adjoint_speedup_vs_f32"] = best[1] / bwd
+    return rec
+
+
+def mixed_comparison(seed, dev, steps, warmup, main=None, main_ref=None, cpu=True):
     """The FP32 forms (Gauss and Pascal) against BF16x3 and FP16x3 on the same
-    inputs: time per launch, speedup over the faster FP32 form, and the
-    largest per-level relative difference from the FP32 (Gauss-form) result.
-    The error against FP64 is checked by the parity tests."""
+    inputs: time per launch, rooflines, speedup over the faster FP32 form and
+    the error per level against the FP64 oracle (whose M2L of the same inputs
+    is timed as that workload's CPU baseline)."""
     out = {}
     for name in MIXED_COMPARE:
-        w = main if (main is not None and main.name == name) else Workload(name, seed, dev)
-        f_ms, f_bwd = w.time_m2l("f32", steps, warmup)
-        ref = w.L.clone()
-        rec = {"outputs": w.outputs, "f32_ms": f_ms, "f32_adjoint_ms": f_bwd}
-        pa_ms, pa_bwd = w.time_m2l("f32_pascal", steps, warmup)
-        rf = roofline(w, "f32_pascal", pa_ms)
-        rec["f32_pascal"] = {"ms": pa_ms, "adjoint_ms": pa_bwd, "max_level_rel_diff_vs_f32": w.level_rel_diff(ref),
-                             "roofline_frac": rf["frac"], "form_roofline_frac": rf["form"]["frac"]}
-        best, best_bwd = min(f_ms, pa_ms), min(f_bwd, pa_bwd)
+        if main is not None and main.name == name:
+            w, ref, base = main, main_ref, None
+        else:
+            w = Workload(name, seed, dev)
+            base, ref = cpu_baseline(w, budget_s=4.0, max_runs=5, single_thread=False) if cpu else (None, None)
+        rec = {"outputs": w.outputs, "translations": w.ntrans}
+        rec["f32"] = precision_block(w, "f32", steps, warmup, ref)
+        rec["f32_pascal"] = precision_block(w, "f32_pascal", steps, warmup, ref)
+        best = (min(rec["f32"]["ms"], rec["f32_pascal"]["ms"]),
+                min(rec["f32"]["adjoint_ms"], rec["f32_pascal"]["adjoint_ms"]))
         for prec in ("bf16x3", "f16x3"):
-            ms, bwd = w.time_m2l(prec, steps, warmup)
-            rec[prec] = {"ms": ms, "adjoint_ms": bwd, "speedup_vs_f32": best / ms,
-                         "adjoint_speedup_vs_f32": best_bwd / bwd,
-                         "max_level_rel_diff_vs_f32": w.level_rel_diff(ref),
-                         "roofline_frac": roofline(w, prec, ms)["frac"]}
+            rec[prec] = precision_block(w, prec, steps, warmup, ref, best)
+        if base is not None:
+            rec["cpu_baseline"] = base
         out[name] = rec
     out["speedup_reference"] = "the faster FP32 form on the same workload"
-    out["tolerance_vs_fp64"] = {"f32": 1e-5, "f32_pascal": 1e-5, "bf16x3": 1e-4, "f16x3": 1e-4}
     return out
+
+
+def large_workload(seed, dev, steps, warmup):
+    """The 2^24-point mixed set, depth 10, p = 20: forward and adjoint M2L in
+    every precision (time, roofline; the error against FP64 is checked by the
+    parity tests), and the whole FMM's forward and reverse stage times in the
+    Pascal form and in BF16x3."""
+    name = "m2l_mixed_n16M_d10_p20"
+    w = Workload(name, seed, dev)
+    out = {"workload": name, "translations": w.ntrans}
+    pa = precision_block(w, "f32_pascal", steps, warmup, None)
+    ga = precision_block(w, "f32", steps, warmup, None)
+    out["f32_pascal"], out["f32"] = pa, ga
+    best = (min(pa["ms"], ga["ms"]), min(pa["adjoint_ms"], ga["adjoint_ms"]))
+    for prec in ("bf16x3", "f16x3"):
+        out[prec] = precision_block(w, prec, steps, warmup, None, best)
+    del w
+    out["fmm_stages_ms"] = {prec: fmm_stage_times(name, prec, seed, dev, reps=3) for prec in ("f32_pascal", "bf16x3")}
+    return out
+
+
+def gradient_timing(seed, dev, reps=5):
+    """Forward plus backward of the loss sum_t (Re phi(z_t))^2 at 4096 uniform
+    targets for 2^20 uniform sources (depth 8, p = 12, FP32 Pascal-form M2L)
+    through the autograd layer: host-clock medians (the tree build
+    synchronises with the host), gradients with respect to charges and
+    positions."""
+    import torch
+
+    import paper_1009_3457_amd as P
+    import synthetic as sy
+    n, depth, p = 1 << 20, 8, 12
+    xy = torch.from_numpy(sy.uniform(n, seed)).to(dev)
+    q = torch.from_numpy(sy.charges(n, seed + 1)).to(dev)
+    t = torch.from_numpy(sy.uniform(4096, seed + 3)).to(dev)
+    fw, bw = [], []
+    for _ in range(reps + 1):
+        xg = xy.clone().requires_grad_(True)
+        qg = q.clone().requires_grad_(True)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        phi, _ = P.potential(xg, qg, t, depth=depth, p=p, precision="f32_pascal")
+        loss = (phi.real ** 2).sum()
+        torch.cuda.synchronize(dev)
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize(dev)
+        t2 = time.perf_counter()
+        fw.append((t1 - t0) * 1e3)
+        bw.append((t2 - t1) * 1e3)
+    fw, bw = sorted(fw[1:]), sorted(bw[1:])
+    return {"workload": "2^20 uniform sources, 4096 uniform targets, depth 8, p 12, f32_pascal",
+            "forward_ms": fw[len(fw) // 2], "backward_ms": bw[len(bw) // 2],
+            "total_ms": fw[len(fw) // 2] + bw[len(bw) // 2], "reps": reps}
 
 
 def fgt_pairs(txy, depth, K):
@@ -410,8 +541,8 @@ def fmm_stage_times(name, prec_name, seed, dev, reps=5):
     as both source and target: tree build (with the sorted gathers), P2M, M2M,
     M2L, L2L, L2P, P2P, then the reverse pass for seeded cotangents of (phi,
     field): L2P^T, L2L^T, M2L^T, M2M^T, P2M^T, P2P^T.  HIP events on the
-    stream; the tree build synchronises with the host (it checks the domain),
-    so it is timed with host clocks."""
+    stream; the tree build leaves its domain check on the device, which is
+    read after the pass."""
     import torch
 
     import paper_1009_3457_amd as P
@@ -428,41 +559,39 @@ def fmm_stage_times(name, prec_name, seed, dev, reps=5):
     rows = []
     for _ in range(reps + 1):
         torch.cuda.synchronize(dev)
-        t0 = time.perf_counter()
-        perm, ls = P.build_tree(xy, depth)
-        xs, qs = P.gather(xy, perm), P.gather(q, perm)
-        torch.cuda.synchronize(dev)
-        t_tree = (time.perf_counter() - t0) * 1e3
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(13)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(14)]
         ev[0].record(stream)
-        M = B.p2m(xs, qs, ls, depth, p)
+        perm, ls, flag = B.build_tree(xy, depth, check=False)
+        xs, qs = P.gather(xy, perm), P.gather(q, perm)
         ev[1].record(stream)
-        B.m2m(M, depth, p)
+        M = B.p2m(xs, qs, ls, depth, p)
         ev[2].record(stream)
-        Lm, bm = B.m2l(M, depth, p, 2, depth, prec)
+        B.m2m(M, depth, p)
         ev[3].record(stream)
-        L, b = B.l2l(Lm, bm, depth, p)
+        Lm, bm = B.m2l(M, depth, p, 2, depth, prec)
         ev[4].record(stream)
-        phi, field = B.l2p(xs, ls, L, b, depth, p)
+        L, b = B.l2l(Lm, bm, depth, p)
         ev[5].record(stream)
-        B.p2p(xs, qs, ls, xs, ls, depth, phi, field)
+        phi, field = B.l2p(xs, ls, L, b, depth, p)
         ev[6].record(stream)
+        B.p2p(xs, qs, ls, xs, ls, depth, phi, field)
+        ev[7].record(stream)
         cphi, cfield = cot[0], cot[1]
         gL, gb = B.l2p_backward(xs, ls, cphi, cfield, depth, p)
-        ev[7].record(stream)
-        gLm, gbm = B.l2l_backward(gL, gb, depth, p)
         ev[8].record(stream)
-        gM = B.m2l_backward(gLm, gbm, depth, p, 2, depth, prec)
+        gLm, gbm = B.l2l_backward(gL, gb, depth, p)
         ev[9].record(stream)
-        B.m2m_backward(gM, depth, p)
+        gM = B.m2l_backward(gLm, gbm, depth, p, 2, depth, prec)
         ev[10].record(stream)
-        gq, G = B.p2m_backward(xs, qs, ls, depth, p, gM)
+        B.m2m_backward(gM, depth, p)
         ev[11].record(stream)
-        B.p2p_backward(xs, qs, ls, xs, ls, depth, cphi, cfield, gq, G)
+        gq, G = B.p2m_backward(xs, qs, ls, depth, p, gM)
         ev[12].record(stream)
+        B.p2p_backward(xs, qs, ls, xs, ls, depth, cphi, cfield, gq, G)
+        ev[13].record(stream)
         torch.cuda.synchronize(dev)
-        st = [ev[i].elapsed_time(ev[i + 1]) for i in range(12)]
-        rows.append([t_tree] + st)
+        B.check_domain(flag)
+        rows.append([ev[i].elapsed_time(ev[i + 1]) for i in range(13)])
     rows = sorted(rows[1:], key=lambda r: sum(r))  # drop the first (warm-up) pass
     med = rows[len(rows) // 2]
     names = ["tree_build_and_gather", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p",
@@ -484,6 +613,8 @@ def main():
     ap.add_argument("--precision", default=None, choices=["f32", "f32_pascal", "bf16x3", "f16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision comparison")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 2^24-point workload and the gradient timing")
     ap.add_argument("--fmm", action="store_true",
                     help="also time every stage of the whole FMM (all points as sources and targets)")
     ap.add_argument("--fgt", default=None, choices=sorted(FGT_WORKLOADS),
@@ -519,9 +650,18 @@ def main():
     # the timed region: K forward M2L launches, bracketed by synchronisation
     ms_fwd, ms_bwd = w.time_m2l(prec_name, args.steps, args.warmup)
     value = w.ntrans / (ms_fwd * 1e-3)
+    launch = w.launch_spread()
     padded = 27 * sum(4 ** l for l in range(2, w.depth + 1))
     default_run = args.workload == DEFAULT and args.precision is None
 
+    # after the timed region: the oracle's M2L of the same inputs, timed on
+    # the host cores, is also the FP64 reference for the error per level
+    base, ref = (None, None)
+    if not args.no_cpu_baseline:
+        base, ref = cpu_baseline(w)
+    err = w.error_vs_fp64(ref)  # w.L still holds the headline launch's result
+
+    rf = roofline(w, prec_name, ms_fwd)
     out = {
         "metric": "M2L Gop/s & translations/s (N=2^20, p=12), % of roofline; mixed vs FP32 at tol",
         "value": value,
@@ -541,25 +681,34 @@ def main():
                    "p": w.p, "levels": f"2..{w.depth}", "precision": prec_name, "outputs": w.outputs,
                    "translations": w.ntrans, "padded_translations": padded, "seed": args.seed},
         "gop_s": 8.0 * w.p * w.p * w.ntrans / (ms_fwd * 1e-3) / 1e9,
-        "roofline": roofline(w, prec_name, ms_fwd),
-        "m2l_launch_ms": w.launch_spread(),
+        "roofline": rf,
+        "error_vs_fp64": err,
+        "tolerance_vs_fp64": TOLERANCE_VS_FP64[prec_name],
+        "m2l_launch_ms": launch,
         "adjoint_ms": ms_bwd,
         "adjoint_translations_per_s": w.ntrans / (ms_bwd * 1e-3),
         "adjoint_roofline_frac": roofline(w, prec_name, ms_bwd)["frac"],
         "paper_context": {"translations_per_s": PAPER_P12_TRANS_PER_S, "gop_s": 511.06,
                           "hardware": "Tesla C1060, FP32, p=12, 2,359,152 translations"},
     }
+    if err is not None:
+        out["within_tolerance"] = err["max"] <= TOLERANCE_VS_FP64[prec_name]
     if default_run and not args.no_mixed:
         out["mixed_vs_f32"] = mixed_comparison(args.seed, dev, max(args.steps // 2, 10),
-                                               max(args.warmup // 2, 2), main=w)
-    if args.fmm:
+                                               max(args.warmup // 2, 2), main=w, main_ref=ref,
+                                               cpu=not args.no_cpu_baseline)
+    if args.fmm or default_run:
         out["fmm_stages_ms"] = fmm_stage_times(args.workload, prec_name, args.seed, dev)
+    if default_run and not args.no_large:
+        out["large_n16M_d10_p20"] = large_workload(args.seed, dev, max(args.steps // 4, 5),
+                                                   max(args.warmup // 4, 2))
+        out["gradient_n1M_4096_targets"] = gradient_timing(args.seed, dev)
     fgt_name = args.fgt or (FGT_DEFAULT if default_run else None)
     if fgt_name:
         out["fgt_hermite"] = fgt_bench(fgt_name, args.seed, dev, max(args.steps // 10, 5),
                                        max(args.warmup // 10, 2), cpu=not args.no_cpu_baseline)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w.M.cpu().numpy(), w.depth, w.p)
+    if base is not None:
+        out["cpu_baseline"] = base
     print(json.dumps(out))
 
 

@@ -37,8 +37,8 @@
  *   unless stated otherwise; the caller allocates and owns it.  No entry point
  *   allocates device memory except fmm2d_build_tree's documented use of the
  *   caller's workspace.  Arrays must not overlap unless stated.
- * Streams.  Work is enqueued on `stream` (0 = the null stream) and returns
- *   without synchronising, except fmm2d_build_tree (see there).
+ * Streams.  Work is enqueued on `stream` (0 = the null stream) and every
+ *   entry point returns without synchronising with the host.
  * Errors.  Every entry point returns FMM2D_OK (0) or a negative
  *   fmm2d_status.  Arguments are validated on the host before any HIP call, so
  *   an invalid call enqueues nothing.  fmm2d_last_error() returns a message for
@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define FMM2D_ABI_VERSION 1
+#define FMM2D_ABI_VERSION 2
 
 typedef enum fmm2d_status {
     FMM2D_OK = 0,
@@ -115,13 +115,17 @@ size_t fmm2d_build_tree_workspace(int64_t n, int depth);
  *   perm        [n] int32 out: perm[i] = original index of the i-th sorted point
  *   leaf_start  [4^depth + 1] int32 out: first sorted index of every leaf;
  *               leaf_start[4^depth] = n
+ *   domain_flag [1] uint32 out (device memory, required): 0 when every point
+ *               lies in [0,1]^2, nonzero when one lies outside or is NaN (then
+ *               perm and leaf_start are unspecified).  It is written on the
+ *               stream like the other outputs; the caller reads it when it
+ *               chooses, so the call never waits for the device.
  *   ws, ws_bytes  caller workspace of at least fmm2d_build_tree_workspace(n, depth)
- * 0 <= n < 2^31.  Synchronises `stream` before returning, to report
- * FMM2D_EDOMAIN when a point is outside [0,1]^2 or NaN (perm and leaf_start
- * are then unspecified).
+ * 0 <= n < 2^31.  Returns without synchronising; FMM2D_EDOMAIN is never
+ * returned by this call (the domain check lives in domain_flag).
  */
 int fmm2d_build_tree(const float *xy, int64_t n, int depth, int32_t *perm, int32_t *leaf_start,
-                     void *ws, size_t ws_bytes, hipStream_t stream);
+                     uint32_t *domain_flag, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* dst[i][c] = src[perm[i]][c] for i < n, c < width (float rows). */
 int fmm2d_gather(const float *src, const int32_t *perm, int64_t n, int width, float *dst,

@@ -36,7 +36,7 @@ _SIGNATURES = {
     "fmm2d_level_offset": (_i64, [_int]),
     "fmm2d_translation_count": (_i64, [_int, _int]),
     "fmm2d_build_tree_workspace": (_sz, [_i64, _int]),
-    "fmm2d_build_tree": (_int, [_vp, _i64, _int, _vp, _vp, _vp, _sz, _vp]),
+    "fmm2d_build_tree": (_int, [_vp, _i64, _int, _vp, _vp, _vp, _vp, _sz, _vp]),
     "fmm2d_gather": (_int, [_vp, _vp, _i64, _int, _vp, _vp]),
     "fmm2d_scatter": (_int, [_vp, _vp, _i64, _int, _vp, _vp]),
     "fmm2d_p2m": (_int, [_vp, _vp, _vp, _int, _int, _vp, _vp]),
@@ -97,10 +97,55 @@ def _stream(device=None):
     return _vp(torch.cuda.current_stream(device).cuda_stream)
 
 
-def _dev(t):
-    if not t.is_cuda:
-        raise ValueError("tensor must be on a GPU device")
-    return t.device
+def _dev(*ts):
+    """The one GPU device all given tensors (None skipped) live on."""
+    ts = [t for t in ts if t is not None]
+    dev = ts[0].device
+    if dev.type != "cuda":
+        raise ValueError("tensors must be on a GPU device")
+    for t in ts[1:]:
+        if t.device != dev:
+            raise ValueError(f"tensors on different devices: {dev} and {t.device}")
+    return dev
+
+
+def _arg(t, name, dtype, shape, optional=False):
+    """Checks one tensor argument against the layout the C ABI reads (dtype,
+    exact shape, contiguity) before any pointer is passed: a wrong dtype would
+    be reinterpreted and a short buffer read or written past its end."""
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    dts = dtype if isinstance(dtype, tuple) else (dtype,)
+    if t.dtype not in dts:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {' or '.join(str(d) for d in dts)}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _depth_ok(depth: int, lo: int = 2) -> int:
+    """The tree entry points take depth 2..12, the fast Gauss transform 0..12."""
+    if not lo <= int(depth) <= 12:
+        raise ValueError(f"depth {depth} outside {lo}..12")
+    return int(depth)
+
+
+def _nleaf1(depth: int) -> int:
+    return (1 << (2 * depth)) + 1
+
+
+def _points(t, name):
+    """[n, 2] float32 points; returns n."""
+    _arg(t, name, torch.float32, None)
+    if t.dim() != 2 or t.shape[1] != 2:
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected (n, 2)")
+    return t.shape[0]
 
 
 # ------------------------------------------------------------ queries ---
@@ -119,47 +164,89 @@ def translation_count(lmin: int, lmax: int) -> int:
 
 # ---------------------------------------------------------------- tree ---
 
-def build_tree(xy: torch.Tensor, depth: int):
-    """Stable leaf sort: returns (perm [n] int32, leaf_start [4^depth+1] int32)."""
+def build_tree(xy: torch.Tensor, depth: int, check: bool = True):
+    """Stable leaf sort: returns (perm [n] int32, leaf_start [4^depth+1] int32).
+
+    The library writes a device-side domain flag instead of waiting for the
+    device.  With check=True it is read here (one wait on the stream) and a
+    point outside [0,1]^2 or NaN raises FMMError; with check=False the flag
+    (uint32 [1], nonzero for such a point) is returned as a third value for
+    the caller to read when it chooses."""
+    n = _points(xy, "xy")
+    depth = _depth_ok(depth)
     dev = _dev(xy)
-    n = xy.shape[0]
     perm = torch.empty(n, dtype=torch.int32, device=dev)
-    ls = torch.empty((1 << (2 * depth)) + 1, dtype=torch.int32, device=dev)
+    ls = torch.empty(_nleaf1(depth), dtype=torch.int32, device=dev)
+    flag = torch.empty(1, dtype=torch.int32, device=dev)
     wsb = int(load().fmm2d_build_tree_workspace(n, depth))
     ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
-    _check(load().fmm2d_build_tree(_p(xy), n, depth, _p(perm), _p(ls), _p(ws), wsb, _stream(dev)))
+    _check(load().fmm2d_build_tree(_p(xy), n, depth, _p(perm), _p(ls), _p(flag), _p(ws), wsb, _stream(dev)))
+    if not check:
+        return perm, ls, flag
+    check_domain(flag)
     return perm, ls
 
 
-def _row_width(src: torch.Tensor) -> int:
-    if src.dtype not in (torch.float32, torch.complex64):
-        raise ValueError("gather/scatter move float32 or complex64 rows")
+def check_domain(*flags):
+    """Raises FMMError when any domain flag from build_tree(check=False) is
+    set (this waits for the stream that wrote it)."""
+    for f in flags:
+        if int(f.item()) != 0:
+            raise FMMError("libfmm2d: a point lies outside [0,1]^2 or is NaN")
+
+
+def _rows(src: torch.Tensor, perm: torch.Tensor):
+    _arg(perm, "perm", torch.int32, None)
+    if perm.dim() != 1:
+        raise ValueError(f"perm: shape {tuple(perm.shape)}, expected (n,)")
+    _arg(src, "src", (torch.float32, torch.complex64), None)
+    if src.dim() < 1 or src.shape[0] != perm.shape[0]:
+        raise ValueError(f"src has {src.shape[0] if src.dim() else 0} rows, perm {perm.shape[0]}")
     per_row = src.numel() // max(src.shape[0], 1)
-    return per_row * (2 if src.is_complex() else 1)
+    return perm.shape[0], per_row * (2 if src.is_complex() else 1)
 
 
 def gather(src: torch.Tensor, perm: torch.Tensor) -> torch.Tensor:
     """dst[i] = src[perm[i]] for float32 / complex64 rows."""
-    n = perm.shape[0]
-    width = _row_width(src)
+    n, width = _rows(src, perm)
+    dev = _dev(src, perm)
     dst = torch.empty_like(src)
-    _check(load().fmm2d_gather(_p(src), _p(perm), n, width, _p(dst), _stream(_dev(src))))
+    _check(load().fmm2d_gather(_p(src), _p(perm), n, width, _p(dst), _stream(dev)))
     return dst
 
 
 def scatter(src: torch.Tensor, perm: torch.Tensor) -> torch.Tensor:
     """dst[perm[i]] = src[i] for float32 / complex64 rows."""
-    n = perm.shape[0]
-    width = _row_width(src)
+    n, width = _rows(src, perm)
+    dev = _dev(src, perm)
     dst = torch.empty_like(src)
-    _check(load().fmm2d_scatter(_p(src), _p(perm), n, width, _p(dst), _stream(_dev(src))))
+    _check(load().fmm2d_scatter(_p(src), _p(perm), n, width, _p(dst), _stream(dev)))
     return dst
+
+
+def _sources(xy_sorted, q_sorted, leaf_start, depth):
+    """Checks the sorted sources of a tree; returns their count."""
+    n = _points(xy_sorted, "xy_sorted")
+    _arg(q_sorted, "q_sorted", torch.float32, (n,))
+    _arg(leaf_start, "leaf_start", torch.int32, (_nleaf1(depth),))
+    return n
+
+
+def _expansion(t, name, depth, p, dtype=torch.complex64, optional=False):
+    return _arg(t, name, dtype, (num_boxes(depth), p), optional)
+
+
+def _per_box(t, name, depth, dtype=torch.complex64, optional=True):
+    return _arg(t, name, dtype, (num_boxes(depth),), optional)
 
 
 # -------------------------------------------------------- upward sweep ---
 
 def p2m(xy_sorted, q_sorted, leaf_start, depth: int, p: int, M=None):
-    dev = _dev(xy_sorted)
+    depth = _depth_ok(depth)
+    _sources(xy_sorted, q_sorted, leaf_start, depth)
+    _expansion(M, "M", depth, p, optional=True)
+    dev = _dev(xy_sorted, q_sorted, leaf_start, M)
     if M is None:
         M = torch.zeros(num_boxes(depth), p, dtype=torch.complex64, device=dev)
     _check(load().fmm2d_p2m(_p(xy_sorted), _p(q_sorted), _p(leaf_start), depth, p, _p(M), _stream(dev)))
@@ -167,6 +254,8 @@ def p2m(xy_sorted, q_sorted, leaf_start, depth: int, p: int, M=None):
 
 
 def m2m(M, depth: int, p: int):
+    depth = _depth_ok(depth)
+    _expansion(M, "M", depth, p)
     _check(load().fmm2d_m2m(_p(M), depth, p, _stream(_dev(M))))
     return M
 
@@ -191,11 +280,25 @@ def m2l_operators(p: int, precision: int, device) -> torch.Tensor:
     return ops
 
 
+def _ops_arg(ops, p, precision):
+    _arg(ops, "ops", torch.uint8, None)
+    need = int(load().fmm2d_m2l_operators_bytes(p, precision))
+    if ops.dim() != 1 or ops.numel() < need:
+        raise ValueError(f"ops: {ops.numel()} bytes, the bank for p={p}, precision={precision} needs {need}")
+    return ops
+
+
 def m2l(M, depth: int, p: int, lmin: int = 2, lmax: int | None = None, precision: int = F32,
         L=None, b=None, with_b: bool = True, ops=None):
     """M2L + reduction on levels lmin..lmax; returns (L, b) (b None if not with_b)."""
-    dev = _dev(M)
+    depth = _depth_ok(depth)
     lmax = depth if lmax is None else lmax
+    _expansion(M, "M", depth, p)
+    _expansion(L, "L", depth, p, optional=True)
+    _per_box(b, "b", depth)
+    if ops is not None:
+        _ops_arg(ops, p, precision)
+    dev = _dev(M, L, b, ops)
     nb = num_boxes(depth)
     if L is None:
         L = torch.zeros(nb, p, dtype=torch.complex64, device=dev)
@@ -210,8 +313,14 @@ def m2l(M, depth: int, p: int, lmin: int = 2, lmax: int | None = None, precision
 def m2l_backward(gL, gb, depth: int, p: int, lmin: int = 2, lmax: int | None = None,
                  precision: int = F32, gM=None, ops=None):
     """Plain transpose of m2l; returns gM (levels lmin..lmax written)."""
-    dev = _dev(gL)
+    depth = _depth_ok(depth)
     lmax = depth if lmax is None else lmax
+    _expansion(gL, "gL", depth, p)
+    _per_box(gb, "gb", depth)
+    _expansion(gM, "gM", depth, p, optional=True)
+    if ops is not None:
+        _ops_arg(ops, p, precision)
+    dev = _dev(gL, gb, gM, ops)
     if gM is None:
         gM = torch.zeros(num_boxes(depth), p, dtype=torch.complex64, device=dev)
     ops = m2l_operators(p, precision, dev) if ops is None else ops
@@ -221,7 +330,10 @@ def m2l_backward(gL, gb, depth: int, p: int, lmin: int = 2, lmax: int | None = N
 
 
 def l2l(Lm2l, bm2l, depth: int, p: int):
-    dev = _dev(Lm2l)
+    depth = _depth_ok(depth)
+    _expansion(Lm2l, "Lm2l", depth, p)
+    _per_box(bm2l, "bm2l", depth)
+    dev = _dev(Lm2l, bm2l)
     nb = num_boxes(depth)
     L = torch.empty(nb, p, dtype=torch.complex128, device=dev)
     b = None if bm2l is None else torch.empty(nb, dtype=torch.complex128, device=dev)
@@ -229,9 +341,19 @@ def l2l(Lm2l, bm2l, depth: int, p: int):
     return L, b
 
 
+def _targets_out(phi, field, nt):
+    _arg(phi, "phi", torch.complex64, (nt,), optional=True)
+    _arg(field, "field", torch.complex64, (nt,), optional=True)
+
+
 def l2p(txy_sorted, tleaf_start, L, b, depth: int, p: int, phi=None, field=None):
-    dev = _dev(L)
-    nt = txy_sorted.shape[0]
+    depth = _depth_ok(depth)
+    nt = _points(txy_sorted, "txy_sorted")
+    _arg(tleaf_start, "tleaf_start", torch.int32, (_nleaf1(depth),))
+    _expansion(L, "L", depth, p, dtype=torch.complex128)
+    _per_box(b, "b", depth, dtype=torch.complex128)
+    _targets_out(phi, field, nt)
+    dev = _dev(txy_sorted, tleaf_start, L, b, phi, field)
     if phi is None:
         phi = torch.zeros(nt, dtype=torch.complex64, device=dev)
     if field is None:
@@ -242,8 +364,12 @@ def l2p(txy_sorted, tleaf_start, L, b, depth: int, p: int, phi=None, field=None)
 
 
 def p2p(xy_sorted, q_sorted, leaf_start, txy_sorted, tleaf_start, depth: int, phi=None, field=None):
-    dev = _dev(xy_sorted)
-    nt = txy_sorted.shape[0]
+    depth = _depth_ok(depth)
+    _sources(xy_sorted, q_sorted, leaf_start, depth)
+    nt = _points(txy_sorted, "txy_sorted")
+    _arg(tleaf_start, "tleaf_start", torch.int32, (_nleaf1(depth),))
+    _targets_out(phi, field, nt)
+    dev = _dev(xy_sorted, q_sorted, leaf_start, txy_sorted, tleaf_start, phi, field)
     if phi is None:
         phi = torch.zeros(nt, dtype=torch.complex64, device=dev)
     if field is None:
@@ -256,7 +382,12 @@ def p2p(xy_sorted, q_sorted, leaf_start, txy_sorted, tleaf_start, depth: int, ph
 # ---------------------------------------------------------- transposes ---
 
 def l2p_backward(txy_sorted, tleaf_start, cphi, cfield, depth: int, p: int):
-    dev = _dev(txy_sorted)
+    depth = _depth_ok(depth)
+    nt = _points(txy_sorted, "txy_sorted")
+    _arg(tleaf_start, "tleaf_start", torch.int32, (_nleaf1(depth),))
+    _arg(cphi, "cphi", torch.complex64, (nt,), optional=True)
+    _arg(cfield, "cfield", torch.complex64, (nt,), optional=True)
+    dev = _dev(txy_sorted, tleaf_start, cphi, cfield)
     nb = num_boxes(depth)
     gL = torch.zeros(nb, p, dtype=torch.complex128, device=dev)
     gb = torch.zeros(nb, dtype=torch.complex128, device=dev)
@@ -266,7 +397,10 @@ def l2p_backward(txy_sorted, tleaf_start, cphi, cfield, depth: int, p: int):
 
 
 def l2l_backward(gL, gb, depth: int, p: int):
-    dev = _dev(gL)
+    depth = _depth_ok(depth)
+    _expansion(gL, "gL", depth, p, dtype=torch.complex128)
+    _per_box(gb, "gb", depth, dtype=torch.complex128)
+    dev = _dev(gL, gb)
     nb = num_boxes(depth)
     gLm = torch.zeros(nb, p, dtype=torch.complex64, device=dev)
     gbm = None if gb is None else torch.zeros(nb, dtype=torch.complex64, device=dev)
@@ -275,13 +409,17 @@ def l2l_backward(gL, gb, depth: int, p: int):
 
 
 def m2m_backward(gM, depth: int, p: int):
+    depth = _depth_ok(depth)
+    _expansion(gM, "gM", depth, p)
     _check(load().fmm2d_m2m_backward(_p(gM), depth, p, _stream(_dev(gM))))
     return gM
 
 
 def p2m_backward(xy_sorted, q_sorted, leaf_start, depth: int, p: int, gM):
-    dev = _dev(xy_sorted)
-    n = xy_sorted.shape[0]
+    depth = _depth_ok(depth)
+    n = _sources(xy_sorted, q_sorted, leaf_start, depth)
+    _expansion(gM, "gM", depth, p)
+    dev = _dev(xy_sorted, q_sorted, leaf_start, gM)
     gq = torch.empty(n, dtype=torch.float32, device=dev)
     G = torch.empty(n, dtype=torch.complex64, device=dev)
     _check(load().fmm2d_p2m_backward(_p(xy_sorted), _p(q_sorted), _p(leaf_start), n, depth, p, _p(gM),
@@ -291,8 +429,15 @@ def p2m_backward(xy_sorted, q_sorted, leaf_start, depth: int, p: int, gM):
 
 def p2p_backward(xy_sorted, q_sorted, leaf_start, txy_sorted, tleaf_start, depth: int, cphi, cfield,
                  gq, G):
-    dev = _dev(xy_sorted)
-    n = xy_sorted.shape[0]
+    depth = _depth_ok(depth)
+    n = _sources(xy_sorted, q_sorted, leaf_start, depth)
+    nt = _points(txy_sorted, "txy_sorted")
+    _arg(tleaf_start, "tleaf_start", torch.int32, (_nleaf1(depth),))
+    _arg(cphi, "cphi", torch.complex64, (nt,), optional=True)
+    _arg(cfield, "cfield", torch.complex64, (nt,), optional=True)
+    _arg(gq, "gq", torch.float32, (n,))
+    _arg(G, "G", torch.complex64, (n,))
+    dev = _dev(xy_sorted, q_sorted, leaf_start, txy_sorted, tleaf_start, cphi, cfield, gq, G)
     _check(load().fmm2d_p2p_backward(_p(xy_sorted), _p(q_sorted), _p(leaf_start), n, _p(txy_sorted),
                                      _p(tleaf_start), depth, _p(cphi), _p(cfield), _p(gq), _p(G),
                                      _stream(dev)))
@@ -303,7 +448,9 @@ def p2p_backward(xy_sorted, q_sorted, leaf_start, txy_sorted, tleaf_start, depth
 
 def fgt_hermite_coeffs(xy_sorted, q_sorted, leaf_start, depth: int, p: int, sigma: float):
     """Hermite coefficients of every box: float32 [4^depth, p, p] ([box, a, b])."""
-    dev = _dev(xy_sorted)
+    depth = _depth_ok(depth, lo=0)
+    _sources(xy_sorted, q_sorted, leaf_start, depth)
+    dev = _dev(xy_sorted, q_sorted, leaf_start)
     A = torch.empty(1 << (2 * depth), p, p, dtype=torch.float32, device=dev)
     _check(load().fgt2d_hermite_coeffs(_p(xy_sorted), _p(q_sorted), _p(leaf_start), depth, p, float(sigma),
                                        _p(A), _stream(dev)))
@@ -312,8 +459,11 @@ def fgt_hermite_coeffs(xy_sorted, q_sorted, leaf_start, depth: int, p: int, sigm
 
 def fgt_hermite_eval(txy, depth: int, p: int, sigma: float, K: int, A, G=None):
     """Hermite-series evaluation at the targets txy [nt, 2]: float32 [nt]."""
-    dev = _dev(A)
-    nt = txy.shape[0]
+    depth = _depth_ok(depth, lo=0)
+    nt = _points(txy, "txy")
+    _arg(A, "A", torch.float32, (1 << (2 * depth), p, p))
+    _arg(G, "G", torch.float32, (nt,), optional=True)
+    dev = _dev(txy, A, G)
     if G is None:
         G = torch.empty(nt, dtype=torch.float32, device=dev)
     _check(load().fgt2d_hermite_eval(_p(txy), nt, depth, p, float(sigma), int(K), _p(A), _p(G),

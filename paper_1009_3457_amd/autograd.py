@@ -43,15 +43,20 @@ def m2l(M, depth: int, p: int, lmin: int = 2, lmax: int | None = None, precision
 
 
 class _Plan:
-    """Sorted sources/targets of one evaluation (a frozen tree)."""
+    """Sorted sources/targets of one evaluation (a frozen tree).  The domain
+    flags of both tree builds stay on the device; `check()` reads them."""
 
     def __init__(self, xy, q, txy, depth):
         self.depth = depth
-        self.perm, self.ls = B.build_tree(xy, depth)
-        self.tperm, self.tls = B.build_tree(txy, depth)
+        self.perm, self.ls, f1 = B.build_tree(xy, depth, check=False)
+        self.tperm, self.tls, f2 = B.build_tree(txy, depth, check=False)
+        self.flags = (f1, f2)
         self.xs = B.gather(xy, self.perm)
         self.qs = B.gather(q, self.perm)
         self.ts = B.gather(txy, self.tperm)
+
+    def check(self):
+        B.check_domain(*self.flags)
 
 
 def fmm_forward(plan: _Plan, p: int, precision: int):
@@ -68,8 +73,6 @@ def fmm_forward(plan: _Plan, p: int, precision: int):
 def fmm_backward(plan: _Plan, p: int, precision: int, gphi, gfield):
     """Returns (grad_q [n], grad_xy [n, 2]) in the original source order."""
     depth = plan.depth
-    dev = plan.xs.device
-    nt = plan.ts.shape[0]
 
     def _cot(g):
         if g is None:
@@ -86,37 +89,63 @@ def fmm_backward(plan: _Plan, p: int, precision: int, gphi, gfield):
     gq = B.scatter(gq, plan.perm)
     G = B.scatter(G, plan.perm)
     gxy = torch.stack([G.real, -G.imag], dim=1).contiguous()
-    del nt, dev
     return gq, gxy
 
 
 class FMMPotential(torch.autograd.Function):
-    """(phi, field) at the targets for sources (xy, q); differentiable in xy and q
-    at a frozen tree.  Targets are treated as constants."""
+    """(phi, field) at the targets for sources (xy, q) at a frozen tree.
+
+    Differentiable in xy and q, and in the target positions txy for a
+    cotangent of phi: phi is holomorphic in the evaluation point z_t with
+    dphi/dz_t = field(z_t), the field this evaluation returns (its far part
+    is the derivative of the L2P series, its near part that of the P2P sum).
+    A cotangent of the field with targets that require a gradient would need
+    dfield/dz_t, which is not computed: that case raises NotImplementedError.
+    """
 
     @staticmethod
     def forward(ctx, xy, q, txy, depth, p, precision):
+        ctx.set_materialize_grads(False)
         xy = xy.detach().contiguous()
         q = q.detach().contiguous()
         txy = txy.detach().contiguous()
         plan = _Plan(xy, q, txy, depth)
         phi, field = fmm_forward(plan, p, precision)
+        plan.check()  # waits once, after every stage has been enqueued
         ctx.plan = plan
         ctx.cfg = (p, precision)
+        ctx.save_for_backward(field)
         return phi, field
 
     @staticmethod
     def backward(ctx, gphi, gfield):
         p, precision = ctx.cfg
-        gq, gxy = fmm_backward(ctx.plan, p, precision, gphi, gfield)
-        return gxy, gq, None, None, None, None
+        need_xy, need_q, need_t = ctx.needs_input_grad[:3]
+        gxy = gq = gt = None
+        if (need_xy or need_q) and (gphi is not None or gfield is not None):
+            gq, gxy = fmm_backward(ctx.plan, p, precision, gphi, gfield)
+        if need_t:
+            if gfield is not None:
+                raise NotImplementedError(
+                    "the gradient with respect to target positions is available for a cotangent of phi "
+                    "only; a cotangent of the field would need its derivative")
+            if gphi is not None:
+                (field,) = ctx.saved_tensors
+                w = gphi.conj() * field  # dl/dx = Re(conj(g) f), dl/dy = Re(conj(g) i f) = -Im(conj(g) f)
+                gt = torch.stack([w.real, -w.imag], dim=1).contiguous()
+        return gxy, gq, gt, None, None, None
 
 
 def potential(xy, q, targets=None, depth: int = 8, p: int = 12, precision="f32"):
     """phi(z) = sum_s q_s log(z - z_s) and field f(z) = sum_s q_s/(z - z_s) at the
     targets (default: the sources, with self-interaction excluded), by the FMM.
 
-    xy [n, 2] and q [n] float32 on the GPU; returns complex64 (phi, field)."""
+    xy [n, 2] and q [n] float32 on the GPU; returns complex64 (phi, field).
+    Gradients (at a frozen tree) flow to q and xy, and to the targets' positions
+    for a loss on phi.  With targets=None the sources are also the evaluation
+    points, so xy's gradient holds both the source-side and the target-side
+    terms; a loss on the field then raises NotImplementedError in backward
+    when xy requires a gradient."""
     prec = B.PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    t = xy.detach() if targets is None else targets
+    t = xy if targets is None else targets
     return FMMPotential.apply(xy, q, t, depth, p, prec)

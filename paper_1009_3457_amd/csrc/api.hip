@@ -103,8 +103,8 @@ size_t fmm2d_build_tree_workspace(int64_t n, int depth) {
   return build_tree_ws_bytes(n, depth);
 }
 
-int fmm2d_build_tree(const float *xy, int64_t n, int depth, int32_t *perm, int32_t *leaf_start, void *ws,
-                     size_t ws_bytes, hipStream_t stream) {
+int fmm2d_build_tree(const float *xy, int64_t n, int depth, int32_t *perm, int32_t *leaf_start,
+                     uint32_t *domain_flag, void *ws, size_t ws_bytes, hipStream_t stream) {
   const char *fn = "fmm2d_build_tree";
   clear_error();
   FMM2D_TRY(check_depth(fn, depth));
@@ -114,10 +114,11 @@ int fmm2d_build_tree(const float *xy, int64_t n, int depth, int32_t *perm, int32
     FMM2D_NONNULL(fn, perm);
   }
   FMM2D_NONNULL(fn, leaf_start);
+  FMM2D_NONNULL(fn, domain_flag);
   FMM2D_NONNULL(fn, ws);
   const size_t need = build_tree_ws_bytes(n, depth);
   if (ws_bytes < need) return set_error(FMM2D_EWORKSPACE, "%s: workspace %zu bytes, %zu needed", fn, ws_bytes, need);
-  return launch_build_tree(xy, n, depth, perm, leaf_start, ws, ws_bytes, stream);
+  return launch_build_tree(xy, n, depth, perm, leaf_start, domain_flag, ws, stream);
 }
 
 static int gather_common(const char *fn, const float *src, const int32_t *perm, int64_t n, int width, float *dst,

@@ -69,7 +69,7 @@ int check_launch(const char *what);  // FMM2D_OK or FMM2D_EHIP after a kernel la
 // Each launcher assumes validated arguments and only enqueues work.
 
 int launch_build_tree(const float *xy, int64_t n, int depth, int32_t *perm, int32_t *leaf_start,
-                      void *ws, size_t ws_bytes, hipStream_t s);
+                      uint32_t *domain_flag, void *ws, hipStream_t s);
 size_t build_tree_ws_bytes(int64_t n, int depth);
 int launch_gather(const float *src, const int32_t *perm, int64_t n, int width, float *dst, bool scatter,
                   hipStream_t s);

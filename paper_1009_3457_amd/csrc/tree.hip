@@ -30,7 +30,6 @@ struct TreeWs {
   int32_t *vals[2];
   uint32_t *count;  // [kDigits][nchunks]
   uint32_t *part;   // [scan_blocks(kDigits * nchunks)]
-  uint32_t *flag;
 };
 
 static TreeWs carve(void *ws, int64_t n) {
@@ -42,8 +41,7 @@ static TreeWs carve(void *ws, int64_t n) {
   w.vals[0] = reinterpret_cast<int32_t *>(p); p += kb;
   w.vals[1] = reinterpret_cast<int32_t *>(p); p += kb;
   w.count = reinterpret_cast<uint32_t *>(p); p += align256(size_t(kDigits) * nchunks_of(n) * 4);
-  w.part = reinterpret_cast<uint32_t *>(p); p += align256(size_t(scan_blocks(int64_t(kDigits) * nchunks_of(n))) * 4);
-  w.flag = reinterpret_cast<uint32_t *>(p);
+  w.part = reinterpret_cast<uint32_t *>(p);
   return w;
 }
 
@@ -51,8 +49,12 @@ size_t build_tree_ws_bytes(int64_t n, int depth) {
   (void)depth;
   const size_t kb = align256(size_t(n) * 4);
   return 4 * kb + align256(size_t(kDigits) * nchunks_of(n) * 4) +
-         align256(size_t(scan_blocks(int64_t(kDigits) * nchunks_of(n))) * 4) + 256;
+         align256(size_t(scan_blocks(int64_t(kDigits) * nchunks_of(n))) * 4);
 }
+
+// The domain flag starts at zero on the stream (a kernel, not a memset, so
+// the call can also be recorded into a graph).
+__global__ void clear_flag_kernel(uint32_t *__restrict__ flag) { *flag = 0u; }
 
 // Leaf key of every point; flags points outside [0,1]^2 (NaN included).
 __global__ void leaf_keys_kernel(const float2 *__restrict__ xy, int64_t n, int depth, uint32_t *__restrict__ keys,
@@ -219,19 +221,17 @@ __global__ void copy_i32_kernel(const int32_t *__restrict__ a, int32_t *__restri
   if (i < n) b[i] = a[i];
 }
 
-int launch_build_tree(const float *xy, int64_t n, int depth, int32_t *perm, int32_t *leaf_start, void *ws,
-                      size_t ws_bytes, hipStream_t s) {
-  (void)ws_bytes;
+int launch_build_tree(const float *xy, int64_t n, int depth, int32_t *perm, int32_t *leaf_start,
+                      uint32_t *domain_flag, void *ws, hipStream_t s) {
   TreeWs w = carve(ws, n);
   const int64_t nleaf = int64_t(1) << (2 * depth);
-  if (hipMemsetAsync(w.flag, 0, sizeof(uint32_t), s) != hipSuccess)
-    return set_error(FMM2D_EHIP, "build_tree: hipMemsetAsync failed");
+  hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, s, domain_flag);
   int cur = 0;
   if (n > 0) {
     const int64_t nchunks = nchunks_of(n);
     const unsigned gblocks = unsigned((n + 255) / 256);
     hipLaunchKernelGGL(leaf_keys_kernel, dim3(gblocks), dim3(256), 0, s, reinterpret_cast<const float2 *>(xy), n,
-                       depth, w.keys[0], w.vals[0], w.flag);
+                       depth, w.keys[0], w.vals[0], domain_flag);
     const int bits = 2 * depth;
     for (int shift = 0; shift < bits; shift += 4) {
       hipLaunchKernelGGL(digit_count_kernel, dim3(unsigned(nchunks)), dim3(kSortThreads), 0, s, w.keys[cur], n,
@@ -248,14 +248,7 @@ int launch_build_tree(const float *xy, int64_t n, int depth, int32_t *perm, int3
   }
   hipLaunchKernelGGL(leaf_start_kernel, dim3(unsigned((nleaf + 1 + 255) / 256)), dim3(256), 0, s, w.keys[cur], n,
                      nleaf, leaf_start);
-  int rc = check_launch("build_tree");
-  if (rc != FMM2D_OK) return rc;
-  uint32_t flag = 0;
-  if (hipMemcpyAsync(&flag, w.flag, sizeof(flag), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return set_error(FMM2D_EHIP, "build_tree: reading the domain flag failed");
-  if (flag) return set_error(FMM2D_EDOMAIN, "build_tree: a point lies outside [0,1]^2 or is NaN");
-  return FMM2D_OK;
+  return check_launch("build_tree");
 }
 
 __global__ void gather_kernel(const float *__restrict__ src, const int32_t *__restrict__ perm, int64_t n, int width,

@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_abi_version_and_queries():
     lib = _lib()
-    assert lib.fmm2d_abi_version() == 1
+    assert lib.fmm2d_abi_version() == 2
     for d in range(0, 13):
         assert lib.fmm2d_num_boxes(d) == (4 ** (d + 1) - 1) // 3
     assert lib.fmm2d_num_boxes(13) == -1
@@ -104,8 +104,9 @@ def test_null_pointers_rejected_on_host():
     assert lib.fmm2d_m2l(FAKE, FAKE, None, 8, 12, 2, 8, 0, FAKE, 1 << 30, None) == -1  # in == out
     assert lib.fmm2d_p2m(None, FAKE, FAKE, 8, 12, FAKE, None) == -1
     assert lib.fmm2d_l2l(FAKE, None, FAKE, FAKE, 8, 12, None) == -1
-    assert lib.fmm2d_build_tree(FAKE, 10, 8, FAKE, FAKE, FAKE, 0, None) == -5
-    assert lib.fmm2d_build_tree(FAKE, -1, 8, FAKE, FAKE, FAKE, 1 << 30, None) == -1
+    assert lib.fmm2d_build_tree(FAKE, 10, 8, FAKE, FAKE, FAKE, FAKE, 0, None) == -5
+    assert lib.fmm2d_build_tree(FAKE, -1, 8, FAKE, FAKE, FAKE, FAKE, 1 << 30, None) == -1
+    assert lib.fmm2d_build_tree(FAKE, 10, 8, FAKE, FAKE, None, FAKE, 1 << 30, None) == -1  # no flag
     assert lib.fmm2d_gather(FAKE, FAKE, 10, 0, ctypes.c_void_p(0x3000), None) == -1
     assert lib.fmm2d_m2l_operators(12, 0, None, 1 << 30, None) == -1
     assert lib.fmm2d_p2p(FAKE, FAKE, FAKE, FAKE, FAKE, -5, 8, FAKE, FAKE, None) == -1
@@ -154,3 +155,54 @@ def test_pascal_form_banks_are_built_for_every_order():
     need = lib.fmm2d_m2l_operators_bytes(12, 3)
     rc = lib.fmm2d_m2l(FAKE, ctypes.c_void_p(0x2000), None, 8, 12, 2, 8, 3, FAKE, need - 1, None)
     assert rc == -5
+
+
+# --------------------------------------------- the binding's own checks ---
+
+def _cpu(*shape, dtype):
+    import torch
+    return torch.zeros(*shape, dtype=dtype)
+
+
+def test_binding_rejects_bad_tensors_before_the_library():
+    """dtype, shape and contiguity are checked against the layout the C ABI
+    reads before any pointer is passed (CPU tensors reach those checks first;
+    only a well-formed call gets as far as the device check)."""
+    import torch
+
+    from paper_1009_3457_amd import _binding as B
+    depth, p = 4, 12
+    nb = B.num_boxes(depth)
+    good_M = _cpu(nb, p, dtype=torch.complex64)
+    cases = [
+        (lambda: B.m2l(_cpu(nb, p, dtype=torch.complex128), depth, p), "dtype"),  # float64 data
+        (lambda: B.m2l(_cpu(nb - 1, p, dtype=torch.complex64), depth, p), "shape"),  # short buffer
+        (lambda: B.m2l(good_M, depth, p, L=_cpu(nb, p - 1, dtype=torch.complex64)), "shape"),
+        (lambda: B.m2l(good_M, depth, p, b=_cpu(nb - 3, dtype=torch.complex64)), "shape"),
+        (lambda: B.m2l(_cpu(p, nb, dtype=torch.complex64).t(), depth, p), "contiguous"),
+        (lambda: B.m2l_backward(good_M, _cpu(nb, dtype=torch.complex128), depth, p), "dtype"),
+        (lambda: B.build_tree(_cpu(10, 2, dtype=torch.float64), depth), "dtype"),
+        (lambda: B.build_tree(_cpu(10, 3, dtype=torch.float32), depth), "shape"),
+        (lambda: B.build_tree(_cpu(10, 2, dtype=torch.float32), 13), "depth"),
+        (lambda: B.p2m(_cpu(10, 2, dtype=torch.float32), _cpu(10, dtype=torch.float64),
+                       _cpu(4 ** depth + 1, dtype=torch.int32), depth, p), "dtype"),
+        (lambda: B.p2m(_cpu(10, 2, dtype=torch.float32), _cpu(10, dtype=torch.float32),
+                       _cpu(4 ** depth, dtype=torch.int32), depth, p), "shape"),
+        (lambda: B.l2p(_cpu(5, 2, dtype=torch.float32), _cpu(4 ** depth + 1, dtype=torch.int32),
+                       _cpu(nb, p, dtype=torch.complex64), None, depth, p), "dtype"),  # L must be FP64
+        (lambda: B.gather(_cpu(10, 2, dtype=torch.float32), _cpu(9, dtype=torch.int32)), "rows"),
+        (lambda: B.gather(_cpu(10, 2, dtype=torch.float32), _cpu(10, dtype=torch.int64)), "dtype"),
+        (lambda: B.p2p_backward(_cpu(10, 2, dtype=torch.float32), _cpu(10, dtype=torch.float32),
+                                _cpu(4 ** depth + 1, dtype=torch.int32), _cpu(3, 2, dtype=torch.float32),
+                                _cpu(4 ** depth + 1, dtype=torch.int32), depth, None, None,
+                                _cpu(9, dtype=torch.float32), _cpu(10, dtype=torch.complex64)), "shape"),
+        (lambda: B.fgt_hermite_eval(_cpu(5, 2, dtype=torch.float32), depth, 5, 0.1, 8,
+                                    _cpu(4 ** depth, 5, 4, dtype=torch.float32)), "shape"),
+        (lambda: B.m2l(good_M, depth, p, ops=_cpu(16, dtype=torch.uint8)), "bytes"),
+    ]
+    for fn, what in cases:
+        with pytest.raises(ValueError, match=what):
+            fn()
+    # a well-formed call on CPU tensors stops at the device check
+    with pytest.raises(ValueError, match="GPU"):
+        B.m2l(good_M, depth, p, L=_cpu(nb, p, dtype=torch.complex64), b=_cpu(nb, dtype=torch.complex64))

@@ -245,3 +245,45 @@ def test_m2l_autograd_matches_adjoint(P):
     ref = np.conj(oracle.unscale_multipoles(oracle.m2l_transpose(W_un, None, depth, p), depth))
     assert rel(Mt.grad.cpu().numpy(), ref) < 1e-5
     del torch
+
+
+@pytest.mark.parametrize("n,depth,p", [(4096, 4, 12), (50000, 6, 12)])
+def test_self_evaluation_gradient_matches_oracle(P, n, depth, p):
+    """targets=None: the sources are the evaluation points, so the position
+    gradient of sum (Re phi)^2 holds the source-side term (the transpose
+    chain) and the target-side term 2 Re phi (Re f, -Im f)."""
+    import synthetic as sy
+    print(f"self-evaluation gradient n={n} depth={depth} p={p}", flush=True)
+    xy = sy.uniform(n, 91)
+    q = sy.charges(n, 92)
+    xg = _t(xy).requires_grad_(True)
+    qg = _t(q).requires_grad_(True)
+    phi, _ = P.potential(xg, qg, None, depth=depth, p=p)
+    (phi.real ** 2).sum().backward()
+    x64, q64 = xy.astype(np.float64), q.astype(np.float64)
+    phir, fr = oracle.fmm(x64, q64, x64, depth, p)
+    gq_r, gxy_src = oracle.fmm_grad(x64, q64, x64, depth, p, (2 * phir.real).astype(np.complex128))
+    w = 2 * phir.real * fr
+    gxy_r = gxy_src + np.stack([w.real, -w.imag], axis=1)
+    assert rel(qg.grad.cpu().numpy(), gq_r) < 1e-5
+    assert rel(xg.grad.cpu().numpy(), gxy_r) < 1e-5
+
+
+def test_target_gradient_matches_oracle(P):
+    """Separate targets that require a gradient: 2 Re phi (Re f, -Im f)."""
+    import synthetic as sy
+    xy, q, t = sy.uniform(4096, 93), sy.charges(4096, 94), sy.uniform(1000, 95)
+    tg = _t(t).requires_grad_(True)
+    phi, _ = P.potential(_t(xy), _t(q), tg, depth=4, p=12)
+    (phi.real ** 2).sum().backward()
+    phir, fr = oracle.fmm(xy.astype(np.float64), q.astype(np.float64), t.astype(np.float64), 4, 12)
+    w = 2 * phir.real * fr
+    assert rel(tg.grad.cpu().numpy(), np.stack([w.real, -w.imag], axis=1)) < 1e-5
+
+
+def test_self_evaluation_field_loss_raises(P):
+    import synthetic as sy
+    xg = _t(sy.uniform(1000, 96)).requires_grad_(True)
+    _, f = P.potential(xg, _t(sy.charges(1000, 97)), None, depth=4, p=8)
+    with pytest.raises(NotImplementedError):
+        (f.real ** 2).sum().backward()

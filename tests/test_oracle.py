@@ -455,3 +455,30 @@ def test_gradient_matches_central_differences():
         an_q.append(gq[s])
     assert _rel(np.array(an_q), np.array(fd_q)) < 1e-9  # l is quadratic in q
     assert _rel(np.array(an_x), np.array(fd_x)) < 2e-3
+
+
+def test_target_position_gradient_is_the_field():
+    """d(Re phi)/dx_t = Re f and d(Re phi)/dy_t = -Im f at a target (phi is
+    holomorphic in z_t with phi' = f), through the FP64 FMM: central
+    differences of l = sum (Re phi)^2 over target positions against
+    2 Re phi (Re f, -Im f), for targets away from leaf edges."""
+    xy, q, t, depth, p = _loss_setup(nt=64)
+    phi, f = oracle.fmm(xy, q, t, depth, p)
+    hstep, side = 1e-6, 2.0 ** depth
+    fd, an = [], []
+    for i in range(t.shape[0]):
+        frac = t[i] * side - np.floor(t[i] * side)
+        if np.any(frac < 1e-3) or np.any(frac > 1 - 1e-3):
+            continue
+        for dim in range(2):
+            a = t.copy(); a[i, dim] += hstep
+            b = t.copy(); b[i, dim] -= hstep
+            la = np.sum(oracle.fmm(xy, q, a, depth, p)[0].real ** 2)
+            lb = np.sum(oracle.fmm(xy, q, b, depth, p)[0].real ** 2)
+            fd.append((la - lb) / (2 * hstep))
+            g = 2 * phi[i].real * f[i]
+            an.append(g.real if dim == 0 else -g.imag)
+        if len(fd) >= 16:
+            break
+    assert len(fd) >= 16
+    assert _rel(np.array(an), np.array(fd)) < 1e-6
