@@ -35,8 +35,9 @@
  *   fmm2d_build_tree; leaf_start has 4^depth + 1 entries.
  * Memory.  Every pointer argument is DEVICE memory on the current HIP device
  *   unless stated otherwise; the caller allocates and owns it.  No entry point
- *   allocates device memory except fmm2d_build_tree's documented use of the
- *   caller's workspace.  Arrays must not overlap unless stated.
+ *   allocates device memory; fmm2d_build_tree sorts in the caller's workspace
+ *   and fmm2d_build_tree_noalloc in a fixed array of the library.  Arrays must
+ *   not overlap unless stated.
  * Streams.  Work is enqueued on `stream` (0 = the null stream) and every
  *   entry point returns without synchronising with the host.
  * Errors.  Every entry point returns FMM2D_OK (0) or a negative
@@ -126,6 +127,26 @@ size_t fmm2d_build_tree_workspace(int64_t n, int depth);
  */
 int fmm2d_build_tree(const float *xy, int64_t n, int depth, int32_t *perm, int32_t *leaf_start,
                      uint32_t *domain_flag, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Most points fmm2d_build_tree_noalloc accepts. */
+#define FMM2D_NOALLOC_MAX_POINTS 4194304
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * fmm2d_build_tree without a workspace argument.  Same arguments and results
+ * as fmm2d_build_tree (perm, leaf_start and domain_flag are still the
+ * caller's); the sort's workspace is a fixed device array of the library,
+ * sized for FMM2D_NOALLOC_MAX_POINTS points (67,371,264 bytes), of which each device
+ * the call runs on holds its own copy until the process ends.  The call
+ * allocates nothing.  0 <= n <= FMM2D_NOALLOC_MAX_POINTS, else
+ * FMM2D_EWORKSPACE (n too large) or FMM2D_EINVAL (n < 0), on the host before
+ * any HIP call.  All calls on one device share its array: calls that overlap
+ * on one device (other streams, other host threads) race and give undefined
+ * results; calls ordered on one stream are safe.
+ */
+int fmm2d_build_tree_noalloc(const float *xy, int64_t n, int depth, int32_t *perm, int32_t *leaf_start,
+                             uint32_t *domain_flag, hipStream_t stream);
 
 /* dst[i][c] = src[perm[i]][c] for i < n, c < width (float rows). */
 int fmm2d_gather(const float *src, const int32_t *perm, int64_t n, int width, float *dst,

@@ -37,6 +37,7 @@ _SIGNATURES = {
     "fmm2d_translation_count": (_i64, [_int, _int]),
     "fmm2d_build_tree_workspace": (_sz, [_i64, _int]),
     "fmm2d_build_tree": (_int, [_vp, _i64, _int, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "fmm2d_build_tree_noalloc": (_int, [_vp, _i64, _int, _vp, _vp, _vp, _vp]),
     "fmm2d_gather": (_int, [_vp, _vp, _i64, _int, _vp, _vp]),
     "fmm2d_scatter": (_int, [_vp, _vp, _i64, _int, _vp, _vp]),
     "fmm2d_p2m": (_int, [_vp, _vp, _vp, _int, _int, _vp, _vp]),
@@ -185,6 +186,28 @@ def build_tree(xy: torch.Tensor, depth: int, check: bool = True):
         return perm, ls, flag
     check_domain(flag)
     return perm, ls
+
+
+NOALLOC_MAX_POINTS = 1 << 22
+
+
+def build_tree_noalloc(xy: torch.Tensor, depth: int, perm=None, leaf_start=None, flag=None):
+    """build_tree through fmm2d_build_tree_noalloc: the sort's workspace is the
+    library's own device array, so the call itself allocates nothing (pass
+    perm [n] int32, leaf_start [4^depth+1] int32 and flag [1] int32 to keep
+    this wrapper from allocating them).  n <= NOALLOC_MAX_POINTS.  Returns
+    (perm, leaf_start, flag); the flag is not read here."""
+    n = _points(xy, "xy")
+    depth = _depth_ok(depth)
+    _arg(perm, "perm", torch.int32, (n,), optional=True)
+    _arg(leaf_start, "leaf_start", torch.int32, (_nleaf1(depth),), optional=True)
+    _arg(flag, "flag", torch.int32, (1,), optional=True)
+    dev = _dev(xy, perm, leaf_start, flag)
+    perm = torch.empty(n, dtype=torch.int32, device=dev) if perm is None else perm
+    leaf_start = torch.empty(_nleaf1(depth), dtype=torch.int32, device=dev) if leaf_start is None else leaf_start
+    flag = torch.empty(1, dtype=torch.int32, device=dev) if flag is None else flag
+    _check(load().fmm2d_build_tree_noalloc(_p(xy), n, depth, _p(perm), _p(leaf_start), _p(flag), _stream(dev)))
+    return perm, leaf_start, flag
 
 
 def check_domain(*flags):

@@ -121,6 +121,23 @@ int fmm2d_build_tree(const float *xy, int64_t n, int depth, int32_t *perm, int32
   return launch_build_tree(xy, n, depth, perm, leaf_start, domain_flag, ws, stream);
 }
 
+int fmm2d_build_tree_noalloc(const float *xy, int64_t n, int depth, int32_t *perm, int32_t *leaf_start,
+                             uint32_t *domain_flag, hipStream_t stream) {
+  const char *fn = "fmm2d_build_tree_noalloc";
+  clear_error();
+  FMM2D_TRY(check_depth(fn, depth));
+  if (n < 0 || n > kNoAllocMaxPoints)
+    return set_error(n < 0 ? FMM2D_EINVAL : FMM2D_EWORKSPACE, "%s: n = %lld outside [0, %lld]", fn, (long long)n,
+                     (long long)kNoAllocMaxPoints);
+  if (n > 0) {
+    FMM2D_NONNULL(fn, xy);
+    FMM2D_NONNULL(fn, perm);
+  }
+  FMM2D_NONNULL(fn, leaf_start);
+  FMM2D_NONNULL(fn, domain_flag);
+  return launch_build_tree_noalloc(xy, n, depth, perm, leaf_start, domain_flag, stream);
+}
+
 static int gather_common(const char *fn, const float *src, const int32_t *perm, int64_t n, int width, float *dst,
                          bool scatter, hipStream_t stream) {
   clear_error();

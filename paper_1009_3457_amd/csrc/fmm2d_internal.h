@@ -68,9 +68,29 @@ int check_launch(const char *what);  // FMM2D_OK or FMM2D_EHIP after a kernel la
 // ------------------------------------------------------------ launchers -----
 // Each launcher assumes validated arguments and only enqueues work.
 
+// Workspace of the tree build's radix sort for n points: keys and values,
+// both double-buffered, the per-chunk digit counts and the scan's block totals.
+namespace tree_ws {
+constexpr int kChunk = 1024;      // items per sort chunk
+constexpr int kDigits = 16;       // values of one 4-bit digit
+constexpr int kScanBlock = 4096;  // values per scan block
+constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+constexpr int64_t nchunks(int64_t n) { return (n + kChunk - 1) / kChunk; }
+constexpr int64_t scan_blocks(int64_t m) { return (m + kScanBlock - 1) / kScanBlock; }
+constexpr size_t bytes(int64_t n) {
+  return 4 * align256(size_t(n) * 4) + align256(size_t(kDigits) * size_t(nchunks(n)) * 4) +
+         align256(size_t(scan_blocks(int64_t(kDigits) * nchunks(n))) * 4);
+}
+}  // namespace tree_ws
+
 int launch_build_tree(const float *xy, int64_t n, int depth, int32_t *perm, int32_t *leaf_start,
                       uint32_t *domain_flag, void *ws, hipStream_t s);
 size_t build_tree_ws_bytes(int64_t n, int depth);
+// The same with the workspace in the library's own device array (n at most
+// kNoAllocMaxPoints); looks the array up on the current device first.
+constexpr int64_t kNoAllocMaxPoints = int64_t(1) << 22;
+int launch_build_tree_noalloc(const float *xy, int64_t n, int depth, int32_t *perm, int32_t *leaf_start,
+                              uint32_t *domain_flag, hipStream_t s);
 int launch_gather(const float *src, const int32_t *perm, int64_t n, int width, float *dst, bool scatter,
                   hipStream_t s);
 

@@ -14,16 +14,17 @@ constexpr int kSortThreads = 256;
 constexpr int kSortRounds = 4;
 constexpr int kChunk = kSortThreads * kSortRounds;  // items per chunk
 constexpr int kDigits = 16;
+static_assert(kChunk == tree_ws::kChunk && kDigits == tree_ws::kDigits, "workspace layout");
 
-static inline int64_t nchunks_of(int64_t n) { return (n + kChunk - 1) / kChunk; }
+using tree_ws::align256;
+constexpr int64_t nchunks_of(int64_t n) { return tree_ws::nchunks(n); }
 
 constexpr int kScanThreads = 256;
 constexpr int kScanPer = 16;                         // values per thread
 constexpr int kScanBlock = kScanThreads * kScanPer;  // 4096 values per block
+static_assert(kScanBlock == tree_ws::kScanBlock, "workspace layout");
 
-static inline int64_t scan_blocks(int64_t m) { return (m + kScanBlock - 1) / kScanBlock; }
-
-static inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+constexpr int64_t scan_blocks(int64_t m) { return tree_ws::scan_blocks(m); }
 
 struct TreeWs {
   uint32_t *keys[2];
@@ -47,9 +48,7 @@ static TreeWs carve(void *ws, int64_t n) {
 
 size_t build_tree_ws_bytes(int64_t n, int depth) {
   (void)depth;
-  const size_t kb = align256(size_t(n) * 4);
-  return 4 * kb + align256(size_t(kDigits) * nchunks_of(n) * 4) +
-         align256(size_t(scan_blocks(int64_t(kDigits) * nchunks_of(n))) * 4);
+  return tree_ws::bytes(n);
 }
 
 // The domain flag starts at zero on the stream (a kernel, not a memset, so

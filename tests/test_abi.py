@@ -107,6 +107,11 @@ def test_null_pointers_rejected_on_host():
     assert lib.fmm2d_build_tree(FAKE, 10, 8, FAKE, FAKE, FAKE, FAKE, 0, None) == -5
     assert lib.fmm2d_build_tree(FAKE, -1, 8, FAKE, FAKE, FAKE, FAKE, 1 << 30, None) == -1
     assert lib.fmm2d_build_tree(FAKE, 10, 8, FAKE, FAKE, None, FAKE, 1 << 30, None) == -1  # no flag
+    # the allocation-free variant: size limit and nulls checked on the host
+    assert lib.fmm2d_build_tree_noalloc(FAKE, (1 << 22) + 1, 8, FAKE, FAKE, FAKE, None) == -5
+    assert lib.fmm2d_build_tree_noalloc(FAKE, -1, 8, FAKE, FAKE, FAKE, None) == -1
+    assert lib.fmm2d_build_tree_noalloc(FAKE, 10, 8, FAKE, FAKE, None, None) == -1
+    assert lib.fmm2d_build_tree_noalloc(FAKE, 10, 1, FAKE, FAKE, FAKE, None) == -3
     assert lib.fmm2d_gather(FAKE, FAKE, 10, 0, ctypes.c_void_p(0x3000), None) == -1
     assert lib.fmm2d_m2l_operators(12, 0, None, 1 << 30, None) == -1
     assert lib.fmm2d_p2p(FAKE, FAKE, FAKE, FAKE, FAKE, -5, 8, FAKE, FAKE, None) == -1
