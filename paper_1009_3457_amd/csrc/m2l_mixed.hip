@@ -359,9 +359,6 @@ __device__ __forceinline__ void mixed_compute(LdsMix<P, ADJ> &sm, float2 *__rest
         const int cur = i & 1;
         if (i + 1 < 27) load_b(i + 1, cur ^ 1);
         if (kCarryA || i + kApf < 27) load_a((i + kApf) % 27, (i + kApf) % kRing);  // next tile restarts at 0
-        // the loads above stay ahead of this offset's products (the
-        // scheduler would otherwise sink them next to their first use)
-        __builtin_amdgcn_sched_barrier(0);
         const int ap = i % kRing;
         // k-steps innermost: each accumulator takes a chain of KS products
         // (chained accumulation issues faster than rotating accumulators)
@@ -372,6 +369,25 @@ __device__ __forceinline__ void mixed_compute(LdsMix<P, ADJ> &sm, float2 *__rest
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
               acc[mt][nt] = mfma16<PREC>(A[ap][mt][C::a_src(ks)], Bf[cur][nt][C::b_src(ks)], acc[mt][nt]);
+        // The wave issues in order, so a burst of loads ahead of the
+        // products would leave the matrix pipe idle while the LDS and vector
+        // memory queues accept them: the loads of the next offsets issue one
+        // after each product instead, under the products already running.
+        {
+          const int nds = (i + 1 < 27) ? NT * C::kUniqueB : 0;
+          const int nvm = (kCarryA || i + kApf < 27) ? MT * C::kUniqueA : 0;
+#pragma unroll
+          for (int q = 0; q < nds; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+          }
+#pragma unroll
+          for (int q = 0; q < nvm; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // one vector-memory read
+          }
+          __builtin_amdgcn_sched_group_barrier(0x008, MT * NT * KS, 0);  // the rest of the products
+        }
         __builtin_amdgcn_sched_barrier(0);
         if (kF16 && i == K::kMid) __syncthreads();  // matches the loader waves' mid-tile barrier
       }

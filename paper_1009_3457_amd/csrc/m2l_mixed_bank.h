@@ -71,6 +71,14 @@ struct MixCfg {
     }
     return ks;
   }
+  // k-steps whose fragments are loaded (the others repeat an earlier one)
+  static constexpr int count_unique(bool a) {
+    int n = 0;
+    for (int ks = 0; ks < KS; ++ks) n += (a ? a_src(ks) : b_src(ks)) == ks;
+    return n;
+  }
+  static constexpr int kUniqueA = count_unique(true);
+  static constexpr int kUniqueB = count_unique(false);
 };
 
 // Bank: section a [slot][mt][ks][lane] 8 x 16-bit;  section ga
