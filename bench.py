@@ -539,8 +539,9 @@ def fgt_bench(name, seed, dev, steps, warmup, cpu=True, cpu_budget_s=12.0):
 def fmm_stage_times(name, prec_name, seed, dev, reps=5):
     """Per-stage times (ms, median of `reps`) of the whole FMM with every point
     as both source and target: tree build (with the sorted gathers), P2M, M2M,
-    M2L, L2L, L2P, P2P, then the reverse pass for seeded cotangents of (phi,
-    field): L2P^T, L2L^T, M2L^T, M2M^T, P2M^T, P2P^T.  HIP events on the
+    M2L, L2L, L2P, P2P, then the reverse pass for seeded cotangents of a
+    loss on Re phi and the field (a real cotangent of phi, a complex one of
+    the field): L2P^T, L2L^T, M2L^T, M2M^T, P2M^T, P2P^T.  HIP events on the
     stream; the tree build leaves its domain check on the device, which is
     read after the pass."""
     import torch
@@ -554,8 +555,12 @@ def fmm_stage_times(name, prec_name, seed, dev, reps=5):
     q = torch.from_numpy(sy.charges(n, seed + 1)).to(dev)
     P.m2l_operators(p, prec, dev)
     stream = torch.cuda.current_stream(dev)
+    # cotangents of a loss on the physical quantities: Re phi (a real
+    # cotangent of phi) and the field (complex)
     gen = torch.Generator().manual_seed(seed + 2)
-    cot = torch.randn(2, n, dtype=torch.complex64, generator=gen).to(dev)
+    cot = torch.randn(2, n, dtype=torch.complex64, generator=gen)
+    cot[0] = cot[0].real.to(torch.complex64)
+    cot = cot.to(dev)
     rows = []
     for _ in range(reps + 1):
         torch.cuda.synchronize(dev)

@@ -473,7 +473,6 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
           lgn.w = g2.w;
         }
       }
-      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         f4_t a = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[mt][0], sr[0], f4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
@@ -527,7 +526,23 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
       // FP32 matrix products and vector instructions do not run concurrently
       // on gfx950, and each switch from one to the other within a wave costs
       // cycles: the step's products go first, as one group, then the vector
-      // work.
+      // work.  The step's LDS reads (the next step's sources and input
+      // scalings, this step's output scalings) issue one after each product:
+      // the wave issues in order, and a burst of them ahead of the products
+      // would hold the matrix pipe while the LDS queue accepts them.
+      // (Not for the p = 20 adjoint: its registers are taken, and the longer
+      // live ranges would spill.)
+      if constexpr (!(ADJ && P > 16)) {
+        constexpr int kMaxDs = 2 * XL::NE + LI / 4 + MT * (LO / 4);
+        const int nds = (j + 1 < NST ? XL::NE * (ST.q2[j + 1] >= 0 ? 2 : 1) + LI / 4 : 0) + MT * (LO / 4);
+#pragma unroll
+        for (int q = 0; q < kMaxDs; ++q) {
+          if (q < nds) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+          }
+        }
+      }
       __builtin_amdgcn_sched_group_barrier(0x008, 4 * S * MT, 0);  // at most: a pair's
       __builtin_amdgcn_sched_group_barrier(0x002, 1 << 12, 0);
       __builtin_amdgcn_sched_barrier(0);

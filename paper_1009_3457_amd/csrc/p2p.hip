@@ -7,22 +7,23 @@
 namespace fmm2d {
 
 // atan2(y, x) for (x, y) != (0, 0): octant reduction to a = min/max in
-// [0, 1] and atan(a) = a P(a^2), P an odd degree-15 polynomial fitted here to
-// atan on [0, 1] (weighted least squares driven towards equal ripple; largest
-// error 1.0e-7 when evaluated in FP32).  Principal branch, (-pi, pi].
+// [0, 1] and atan(a) = a P(a^2), P the degree-7 minimax polynomial (Remez
+// exchange on the odd basis a^(2j+1); fit_atan.py beside this file computes
+// the coefficients): largest error 3.7e-8 in exact arithmetic, 1.5e-7
+// evaluated in FP32.  Principal branch, (-pi, pi].
 __device__ inline float atan2_p2p(float y, float x) {
   const float ax = fabsf(x), ay = fabsf(y);
   const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
   const float a = mn * __builtin_amdgcn_rcpf(mx);
   const float t = a * a;
-  float r = -0.00405455008f;
-  r = fmaf(r, t, 0.0218629036f);
-  r = fmaf(r, t, -0.0559122637f);
-  r = fmaf(r, t, 0.0964219347f);
-  r = fmaf(r, t, -0.139086291f);
-  r = fmaf(r, t, 0.199465662f);
-  r = fmaf(r, t, -0.333298594f);
-  r = fmaf(r, t, 0.999999344f);
+  float r = -0.004054567310959101f;
+  r = fmaf(r, t, 0.021862957626581192f);
+  r = fmaf(r, t, -0.0559123270213604f);
+  r = fmaf(r, t, 0.0964219719171524f);
+  r = fmaf(r, t, -0.1390862911939621f);
+  r = fmaf(r, t, 0.19946566224098206f);
+  r = fmaf(r, t, -0.33329859375953674f);
+  r = fmaf(r, t, 0.9999993443489075f);
   r *= a;
   if (ay > ax) r = 1.57079632679f - r;
   if (x < 0.f) r = 3.14159265359f - r;
@@ -53,17 +54,21 @@ __device__ inline float phase_sum(float v, const ChunkLanes &c, int lane) {
 // One wave per target leaf.  Targets go in chunks of up to 64; the lanes of a
 // chunk of n targets are split into n targets x 64 / n source phases: lane
 // (i, ph) sums sources ph, ph + nph, ... of each of the 3x3 neighbour leaves
-// for target i, and the phases are then combined in a fixed order.  All
-// lanes read the same few sources at a time, so source loads are served once
-// per wave.  Only the target's own leaf can hold a source at the target's
+// for target i, and the phases are then combined in a fixed order.  The
+// sources of a neighbour leaf pass through the wave's own slice of LDS, 64 at
+// a time (one coalesced load per array), and the lanes read them from there:
+// a global load per pair would cost each pair a trip through the vector
+// memory path.  Only the target's own leaf can hold a source at the target's
 // position; that pair is skipped.
 template <bool PHI, bool FIELD>
 __global__ __launch_bounds__(256) void p2p_kernel(const float2 *__restrict__ xy, const float *__restrict__ q,
                                                   const int32_t *__restrict__ ls, const float2 *__restrict__ txy,
                                                   const int32_t *__restrict__ tls, int depth,
                                                   float2 *__restrict__ phi, float2 *__restrict__ field) {
+  __shared__ float4 stage[4][64];  // per wave: (x, y, q, -) of up to 64 sources
   const int64_t nleaf = int64_t(1) << (2 * depth);
-  const int64_t leaf = blockIdx.x * int64_t(4) + (threadIdx.x >> 6);
+  const int wave = threadIdx.x >> 6;
+  const int64_t leaf = blockIdx.x * int64_t(4) + wave;
   if (leaf >= nleaf) return;
   const int lane = threadIdx.x & 63;
   const int32_t t0 = tls[leaf], nt = tls[leaf + 1] - t0;
@@ -80,6 +85,7 @@ __global__ __launch_bounds__(256) void p2p_kernel(const float2 *__restrict__ xy,
     sb[d] = in ? ls[sm] : 0;
     se[d] = in ? ls[sm + 1] : 0;
   }
+  float4 *st = stage[wave];
   constexpr float kHalfLn2 = 0.346573590279972654709f;  // log(r2) / 2 = kHalfLn2 log2(r2)
   for (int32_t c0 = 0; c0 < nt; c0 += 64) {
     const ChunkLanes cl(nt - c0 < 64 ? nt - c0 : 64, lane);
@@ -90,26 +96,37 @@ __global__ __launch_bounds__(256) void p2p_kernel(const float2 *__restrict__ xy,
     float pr = 0.f, pi = 0.f, fr = 0.f, fi = 0.f;
 #pragma unroll
     for (int d = 0; d < 9; ++d) {
-      for (int32_t s = act ? sb[d] + ph : se[d]; s < se[d]; s += nph) {
-        const float2 zs = xy[s];
-        const float rx = z.x - zs.x, ry = z.y - zs.y;
-        const float r2 = fmaf(rx, rx, ry * ry);
-        float qs = q[s], r2s = r2, ax = rx;
-        if (d == 4) {  // own leaf: a coincident pair is skipped
-          const bool self = r2 == 0.f;
-          qs = self ? 0.f : qs;
-          r2s = self ? 1.f : r2;
-          ax = self ? 1.f : rx;
+      for (int32_t b0 = sb[d]; b0 < se[d]; b0 += 64) {  // the same trip count in every lane
+        const int m = se[d] - b0 < 64 ? se[d] - b0 : 64;
+        if (lane < m) {
+          const float2 zs = xy[b0 + lane];
+          st[lane] = make_float4(zs.x, zs.y, q[b0 + lane], 0.f);
         }
-        if (PHI) {
-          pr = fmaf(qs, __builtin_amdgcn_logf(r2s), pr);  // hardware log2
-          pi = fmaf(qs, atan2_p2p(ry, ax), pi);
+        __builtin_amdgcn_wave_barrier();
+        for (int k = act ? ph : m; k < m; k += nph) {
+          const float4 sv = st[k];
+          const float rx = z.x - sv.x, ry = z.y - sv.y;
+          const float r2 = fmaf(rx, rx, ry * ry);
+          float qs = sv.z, r2s = r2, ax = rx;
+          if (d == 4) {  // own leaf: a coincident pair is skipped
+            const bool self = r2 == 0.f;
+            qs = self ? 0.f : qs;
+            r2s = self ? 1.f : r2;
+            ax = self ? 1.f : rx;
+          }
+          if (PHI) {
+            pr = fmaf(qs, __builtin_amdgcn_logf(r2s), pr);  // hardware log2
+            pi = fmaf(qs, atan2_p2p(ry, ax), pi);
+          }
+          if (FIELD) {
+            const float inv = qs * __builtin_amdgcn_rcpf(r2s);  // hardware reciprocal (1 ulp)
+            fr = fmaf(inv, rx, fr);
+            fi = fmaf(-inv, ry, fi);
+          }
         }
-        if (FIELD) {
-          const float inv = qs * __builtin_amdgcn_rcpf(r2s);  // hardware reciprocal (1 ulp)
-          fr = fmaf(inv, rx, fr);
-          fi = fmaf(-inv, ry, fi);
-        }
+        // every lane's reads of this batch are issued before the next
+        // batch's writes (the wave's LDS accesses complete in order)
+        __builtin_amdgcn_wave_barrier();
       }
     }
     if (nph > 1) {  // combine the phases: lane ph = 0 ends with the total
@@ -137,8 +154,9 @@ __global__ __launch_bounds__(256) void p2p_kernel(const float2 *__restrict__ xy,
 
 // P2P^T with the same layout: one wave per source leaf, sources in chunks of
 // up to 64, each chunk's lanes split into sources x target phases over the
-// 3x3 neighbour leaves.  For the
-// pair r = z_t - z_s and cotangents (c, e) of (phi, field) at target t:
+// 3x3 neighbour leaves, the targets (positions and cotangents) passing
+// through the wave's LDS slice 64 at a time.  For the pair r = z_t - z_s and
+// cotangents (c, e) of (phi, field) at target t:
 //   dq_s += Re(c log r) + Re(e / r),   G_s += q_s (-c / r + e / r^2),
 // G_s being conj of the position gradient packed as dRe + i dIm.
 template <bool CPHI, bool CF>
@@ -149,8 +167,13 @@ __global__ __launch_bounds__(256) void p2p_backward_kernel(const float2 *__restr
                                                            const float2 *__restrict__ cphi,
                                                            const float2 *__restrict__ cfield, float *__restrict__ gq,
                                                            float2 *__restrict__ G) {
+  // per wave, up to 64 targets: (x, y, and the cotangent of phi, or of the
+  // field when phi has none), and the field's when both are present
+  __shared__ float4 stage[4][64];
+  __shared__ float2 stage2[4][CPHI && CF ? 64 : 1];
   const int64_t nleaf = int64_t(1) << (2 * depth);
-  const int64_t leaf = blockIdx.x * int64_t(4) + (threadIdx.x >> 6);
+  const int wave = threadIdx.x >> 6;
+  const int64_t leaf = blockIdx.x * int64_t(4) + wave;
   if (leaf >= nleaf) return;
   const int lane = threadIdx.x & 63;
   const int32_t s0 = ls[leaf], ns = ls[leaf + 1] - s0;
@@ -167,6 +190,8 @@ __global__ __launch_bounds__(256) void p2p_backward_kernel(const float2 *__restr
     tb[d] = in ? tls[tm] : 0;
     te[d] = in ? tls[tm + 1] : 0;
   }
+  float4 *st = stage[wave];
+  float2 *st2 = stage2[wave];
   constexpr float kHalfLn2 = 0.346573590279972654709f;  // log(r2) / 2 = kHalfLn2 log2(r2)
   for (int32_t c0 = 0; c0 < ns; c0 += 64) {
     const ChunkLanes cl(ns - c0 < 64 ? ns - c0 : 64, lane);
@@ -177,35 +202,51 @@ __global__ __launch_bounds__(256) void p2p_backward_kernel(const float2 *__restr
     float alog = 0.f, aang = 0.f, aq = 0.f, gr = 0.f, gi = 0.f;
 #pragma unroll
     for (int d = 0; d < 9; ++d) {
-      for (int32_t t = act ? tb[d] + ph : te[d]; t < te[d]; t += nph) {
-        const float2 z = txy[t];
-        const float rx = z.x - zs.x, ry = z.y - zs.y;
-        const float r2 = fmaf(rx, rx, ry * ry);
-        // own leaf: a coincident pair is skipped
-        const bool self = d == 4 && r2 == 0.f;
-        const float r2s = self ? 1.f : r2;
-        const float inv = __builtin_amdgcn_rcpf(r2s);
-        const float ir = rx * inv, ii = -ry * inv;  // 1/r
-        // G_s gathers (-c + e / r) / r: w = -c + e / r, then w times 1/r
-        float wr = 0.f, wi = 0.f;
-        if (CPHI) {
-          const float2 c0v = cphi[t];
-          const float cx = self ? 0.f : c0v.x, cy = self ? 0.f : c0v.y;
-          alog = fmaf(cx, __builtin_amdgcn_logf(r2s), alog);  // hardware log2
-          aang = fmaf(cy, atan2_p2p(ry, self ? 1.f : rx), aang);
-          wr = -cx;
-          wi = -cy;
+      for (int32_t b0 = tb[d]; b0 < te[d]; b0 += 64) {  // the same trip count in every lane
+        const int m = te[d] - b0 < 64 ? te[d] - b0 : 64;
+        if (lane < m) {
+          const float2 z = txy[b0 + lane];
+          const float2 c = CPHI ? cphi[b0 + lane] : cfield[b0 + lane];
+          st[lane] = make_float4(z.x, z.y, c.x, c.y);
+          if (CPHI && CF) st2[lane] = cfield[b0 + lane];
         }
-        if (CF) {
-          const float2 e0 = cfield[t];
-          const float ex = self ? 0.f : e0.x, ey = self ? 0.f : e0.y;
-          const float ur = fmaf(ex, ir, -ey * ii), ui = fmaf(ex, ii, ey * ir);  // e / r
-          aq += ur;
-          wr += ur;
-          wi += ui;
+        __builtin_amdgcn_wave_barrier();
+        for (int k = act ? ph : m; k < m; k += nph) {
+          const float4 tv = st[k];
+          const float2 e0 = CPHI && CF ? st2[k] : make_float2(tv.z, tv.w);
+          const float rx = tv.x - zs.x, ry = tv.y - zs.y;
+          const float r2 = fmaf(rx, rx, ry * ry);
+          // own leaf: a coincident pair is skipped
+          const bool self = d == 4 && r2 == 0.f;
+          const float r2s = self ? 1.f : r2;
+          const float inv = __builtin_amdgcn_rcpf(r2s);
+          const float ir = rx * inv, ii = -ry * inv;  // 1/r
+          // G_s gathers (-c + e / r) / r: w = -c + e / r, then w times 1/r
+          float wr = 0.f, wi = 0.f, cy = 0.f;
+          if (CPHI) {
+            const float cx = self ? 0.f : tv.z;
+            cy = self ? 0.f : tv.w;
+            alog = fmaf(cx, __builtin_amdgcn_logf(r2s), alog);  // hardware log2
+            wr = -cx;
+            wi = -cy;
+          }
+          if (CF) {
+            const float ex = self ? 0.f : e0.x, ey = self ? 0.f : e0.y;
+            const float ur = fmaf(ex, ir, -ey * ii), ui = fmaf(ex, ii, ey * ir);  // e / r
+            aq += ur;
+            wr += ur;
+            wi += ui;
+          }
+          gr = fmaf(wr, ir, fmaf(-wi, ii, gr));
+          gi = fmaf(wr, ii, fmaf(wi, ir, gi));
+          // Re(c log r) needs the angle of r only for a cotangent with an
+          // imaginary part (a loss on Im phi); for the common real one (a
+          // loss on Re phi) it is skipped whenever no active lane has one
+          if (CPHI && __ballot(cy != 0.f) != 0ull) aang = fmaf(cy, atan2_p2p(ry, self ? 1.f : rx), aang);
         }
-        gr = fmaf(wr, ir, fmaf(-wi, ii, gr));
-        gi = fmaf(wr, ii, fmaf(wi, ir, gi));
+        // every lane's reads of this batch are issued before the next
+        // batch's writes (the wave's LDS accesses complete in order)
+        __builtin_amdgcn_wave_barrier();
       }
     }
     if (nph > 1) {  // combine the phases: lane ph = 0 ends with the total

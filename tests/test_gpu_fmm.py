@@ -154,6 +154,18 @@ def test_p2p_leaf_sizes_match_oracle(P):
     gqr, Gr = oracle.p2p_transpose(X, Q, lr, T, tlr, depth, c.astype(np.complex128), e.astype(np.complex128))
     assert rel(gq.cpu().numpy(), gqr) < 1e-5
     assert rel(G.cpu().numpy(), Gr) < 1e-5
+    # a real cotangent of phi (the kernel skips the angle term), and one with
+    # an imaginary part on a few targets only (lanes of one wave differ)
+    c_real = c.real.astype(np.complex64)
+    c_few = c_real.copy()
+    c_few[::7] = c[::7]
+    for cc in (c_real, c_few):
+        gq.zero_()
+        G.zero_()
+        P.p2p_backward(xs, qs, ls, ts, tls, depth, _t(cc), _t(e), gq, G)
+        gqr, Gr = oracle.p2p_transpose(X, Q, lr, T, tlr, depth, cc.astype(np.complex128), e.astype(np.complex128))
+        assert rel(gq.cpu().numpy(), gqr) < 1e-5
+        assert rel(G.cpu().numpy(), Gr) < 1e-5
 
 
 # ---------------------------------------------------------- pipeline ---
