@@ -63,10 +63,11 @@ WORKLOADS = {
 }
 DEFAULT = "m2l_uniform_n1M_d8_p12"
 MIXED_COMPARE = ["m2l_uniform_n1M_d8_p12", "m2l_mixed_n4M_d9_p16"]
-PEAK_TFLOPS = {"f32": 157.3, "f32_pascal": 157.3, "bf16x3": 2500.0, "f16x3": 2500.0}  # MI355X dense MFMA
-MFMA_FLOPS_FACTOR = {"f32": 1, "f32_pascal": 1, "bf16x3": 3, "f16x3": 3}  # split products per real product
+# MI355X peaks: dense MFMA for the matrix-core forms; FP64 vector arithmetic
+# for the Hankel form, which runs on the vector ALUs
+PEAK_TFLOPS = {"f32": 157.3, "f32_pascal": 157.3, "bf16x3": 2500.0, "f16x3": 2500.0, "f64_hankel": 78.6}
 PEAK_HBM_GBS = 8000.0
-TOLERANCE_VS_FP64 = {"f32": 1e-5, "f32_pascal": 1e-5, "bf16x3": 1e-4, "f16x3": 1e-4}
+TOLERANCE_VS_FP64 = {"f32": 1e-5, "f32_pascal": 1e-5, "bf16x3": 1e-4, "f16x3": 1e-4, "f64_hankel": 1e-5}
 PAPER_P12_TRANS_PER_S = 80.05e6  # Tesla C1060, p = 12, depth-8 tree (Table tab:m2ltesla)
 
 # Fast Gauss transform, Hermite evaluation: name -> (depth, p, K).  Sources and
@@ -90,6 +91,9 @@ def m2l_kernel_sources(precision="f32"):
     names = ["m2l_f32.hip", "m2l_stage.h", "m2l_bank.h", "m2l_common.h", "fmm2d_internal.h"]
     if precision == "f32_pascal":
         names = ["m2l_pascal.hip", "m2l_pascal_bank.h", "m2l_stage.h", "m2l_bank.h", "m2l_common.h",
+                 "fmm2d_internal.h"]
+    elif precision == "f64_hankel":
+        names = ["m2l_hankel.hip", "m2l_hankel_bank.h", "m2l_logrow.hip", "m2l_bank.h", "m2l_common.h",
                  "fmm2d_internal.h"]
     elif precision != "f32":
         names = ["m2l_mixed.hip", "m2l_mixed_bank.h", "m2l_bank.h", "m2l_common.h", "fmm2d_internal.h"]
@@ -323,8 +327,18 @@ def own_flops_per_translation(p, prec_name, outputs):
       6p^2, and the p additions forming Xr + Xi; the log row is one more row
       of the three products (6p) plus the M~_0 sum for the log(h) term (2).
     * Split precision (BF16x3, FP16x3): three real products with the 2p x 2p
-      real embedding, 24p^2, and 24p for the log row's two real rows."""
+      real embedding, 24p^2, and 24p for the log row's two real rows.
+    * Hankel form (FP64): counted per target and divided by its 27
+      translations: the source transforms (144 records per 64 targets, each
+      N = 2p frequencies by p - 1 complex multiply-adds, plus the scaling),
+      27 N complex multiply-adds of spectra, and the p inverse-transform
+      outputs (N - 1 complex multiply-adds each, plus the scaling); the log
+      row, in its own pass, adds 8p + 2."""
     with_b = outputs == "Lb"
+    if prec_name == "f64_hankel":
+        n = 2 * p
+        per_target = (144 / 64) * (n * (p - 1) * 8 + 2 * p) + 27 * n * 8 + p * (n - 1) * 8 + 2 * p
+        return per_target / 27 + (8 * p + 2 if with_b else 0)
     if prec_name == "f32_pascal":
         return 4 * p * p + 14 * p + (4 * p + 8 if with_b else 0)
     if prec_name == "f32":
@@ -343,7 +357,7 @@ def roofline(w, prec_name, ms):
     boxes = sum(4 ** l for l in range(2, w.depth + 1))
     alg_bytes = boxes * w.p * 8 * 2 + (boxes * 8 if w.outputs == "Lb" else 0)
     peak = PEAK_TFLOPS[prec_name]
-    return {"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s", "frac": tflops / peak,
+    return {"bound": "alu" if prec_name == "f64_hankel" else "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s", "frac": tflops / peak,
             "flops_per_translation": own,
             "effective_frac": eff / peak, "dense_flops_per_translation": dense,
             "traffic": recorded_traffic(w.name, prec_name),
@@ -371,8 +385,8 @@ def precision_block(w, prec, steps, warmup, ref, best=None):
 
 
 def mixed_comparison(seed, dev, steps, warmup, main=None, main_ref=None, cpu=True):
-    """The FP32 forms (Gauss and Pascal) against BF16x3 and FP16x3 on the same
-    inputs: time per launch, rooflines, speedup over the faster FP32 form and
+    """The FP32 forms (Gauss and Pascal) against BF16x3, FP16x3 and the FP64
+    Hankel form on the same inputs: time per launch, rooflines, speedup over the faster FP32 form and
     the error per level against the FP64 oracle (whose M2L of the same inputs
     is timed as that workload's CPU baseline)."""
     out = {}
@@ -387,7 +401,7 @@ def mixed_comparison(seed, dev, steps, warmup, main=None, main_ref=None, cpu=Tru
         rec["f32_pascal"] = precision_block(w, "f32_pascal", steps, warmup, ref)
         best = (min(rec["f32"]["ms"], rec["f32_pascal"]["ms"]),
                 min(rec["f32"]["adjoint_ms"], rec["f32_pascal"]["adjoint_ms"]))
-        for prec in ("bf16x3", "f16x3"):
+        for prec in ("bf16x3", "f16x3", "f64_hankel"):
             rec[prec] = precision_block(w, prec, steps, warmup, ref, best)
         if base is not None:
             rec["cpu_baseline"] = base
@@ -398,7 +412,7 @@ def mixed_comparison(seed, dev, steps, warmup, main=None, main_ref=None, cpu=Tru
 
 def large_workload(seed, dev, steps, warmup):
     """The 2^24-point mixed set, depth 10, p = 20: forward and adjoint M2L in
-    every precision (time, roofline; the error against FP64 is checked by the
+    every form (the FP64 Hankel form included) (time, roofline; the error against FP64 is checked by the
     parity tests), and the whole FMM's forward and reverse stage times in the
     Pascal form and in BF16x3."""
     name = "m2l_mixed_n16M_d10_p20"
@@ -408,7 +422,7 @@ def large_workload(seed, dev, steps, warmup):
     ga = precision_block(w, "f32", steps, warmup, None)
     out["f32_pascal"], out["f32"] = pa, ga
     best = (min(pa["ms"], ga["ms"]), min(pa["adjoint_ms"], ga["adjoint_ms"]))
-    for prec in ("bf16x3", "f16x3"):
+    for prec in ("bf16x3", "f16x3", "f64_hankel"):
         out[prec] = precision_block(w, prec, steps, warmup, None, best)
     del w
     out["fmm_stages_ms"] = {prec: fmm_stage_times(name, prec, seed, dev, reps=3) for prec in ("f32_pascal", "bf16x3")}
@@ -615,7 +629,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default=None, choices=["f32", "f32_pascal", "bf16x3", "f16x3"])
+    ap.add_argument("--precision", default=None, choices=["f32", "f32_pascal", "bf16x3", "f16x3", "f64_hankel"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision comparison")
     ap.add_argument("--no-large", action="store_true",

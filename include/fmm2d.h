@@ -72,16 +72,21 @@ typedef enum fmm2d_status {
 } fmm2d_status;
 
 /* Arithmetic of the M2L contraction.  The operators are always generated in
- * FP64 and rounded once; accumulation is always FP32. */
+ * FP64 and rounded once; accumulation is FP32 except in FMM2D_F64_HANKEL. */
 typedef enum fmm2d_precision {
     FMM2D_F32 = 0,     /* FP32 products (MFMA f32)                                   */
     FMM2D_BF16X3 = 1,  /* BF16 hi/lo split of both operands, 3 MFMA products (hi*hi,   */
                        /* hi*lo, lo*hi), FP32 accumulation                             */
     FMM2D_F16X3 = 2,   /* the same with FP16 and power-of-two pre-scaling              */
-    FMM2D_F32_PASCAL = 3  /* FP32 products on the factorisation                        */
+    FMM2D_F32_PASCAL = 3, /* FP32 products on the factorisation                        */
                           /*   A~(d) = diag((-1)^n d^-(n+1)) B diag(d^-k),              */
                           /*   B[n][k] = C(n+k, k): two real MFMA products with the     */
                           /*   constant B per translation, the diagonals on the VALU   */
+    FMM2D_F64_HANKEL = 4  /* FP64 arithmetic on the Hankel form of Eq. (eq:M2Lmat)      */
+                          /*   (entries depend on n + k between two diagonals): the    */
+                          /*   list's translations summed as spectra of length 2p,     */
+                          /*   27 complex multiply-adds per target and frequency;      */
+                          /*   accumulation in FP64, not FP32                          */
 } fmm2d_precision;
 
 /* ----------------------------------------------------------- queries ---- */

@@ -17,8 +17,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfmm2d.so")
 
-F32, BF16X3, F16X3, F32_PASCAL = 0, 1, 2, 3
-PRECISIONS = {"f32": F32, "bf16x3": BF16X3, "f16x3": F16X3, "f32_pascal": F32_PASCAL}
+F32, BF16X3, F16X3, F32_PASCAL, F64_HANKEL = 0, 1, 2, 3, 4
+PRECISIONS = {"f32": F32, "bf16x3": BF16X3, "f16x3": F16X3, "f32_pascal": F32_PASCAL, "f64_hankel": F64_HANKEL}
 
 _lock = threading.Lock()
 _lib = None

@@ -56,7 +56,7 @@ static int check_levels(const char *fn, int depth, int lmin, int lmax) {
 
 static int check_precision(const char *fn, int p, int precision, const void *ops, size_t ops_bytes) {
   if (precision != FMM2D_F32 && precision != FMM2D_BF16X3 && precision != FMM2D_F16X3 &&
-      precision != FMM2D_F32_PASCAL)
+      precision != FMM2D_F32_PASCAL && precision != FMM2D_F64_HANKEL)
     return set_error(FMM2D_EINVAL, "%s: unknown precision %d", fn, precision);
   const size_t need = m2l_ops_bytes(p, precision);
   if (need == 0)
@@ -205,6 +205,8 @@ static int m2l_common(const char *fn, const float *in, const float *gb_in, float
   if (precision == FMM2D_F32) return launch_m2l_f32(in, gb_in, out, b, depth, p, lmin, lmax, adjoint, ops, stream);
   if (precision == FMM2D_F32_PASCAL)
     return launch_m2l_pascal(in, gb_in, out, b, depth, p, lmin, lmax, adjoint, ops, stream);
+  if (precision == FMM2D_F64_HANKEL)
+    return launch_m2l_hankel(in, gb_in, out, b, depth, p, lmin, lmax, adjoint, ops, stream);
   return launch_m2l_mixed(in, gb_in, out, b, depth, p, lmin, lmax, adjoint, precision, ops, stream);
 }
 

@@ -125,6 +125,11 @@ int num_cus();  // compute units of the current device
 // (complex FP32, slot = (ox+3) + 7 (oy+3)); used when the MFMA tiles have no
 // spare rows for it
 int launch_m2l_logrow_fwd(const float *M, float *b, int p, int lmin, int lmax, const float *r, hipStream_t s);
+// its transpose, added into gM for every source box of levels lmin..lmax
+int launch_m2l_logrow_bwd(const float *gb, float *gM, int p, int lmin, int lmax, const float *r, hipStream_t s);
+// the Hankel form (FP64 frequency-domain accumulation), with the log row's pass
+int launch_m2l_hankel(const float *M, const float *gb_in, float *L, float *b, int depth, int p, int lmin, int lmax,
+                      bool adjoint, const void *ops, hipStream_t s);
 int launch_m2l_mixed(const float *M, const float *gb_in, float *L, float *b, int depth, int p, int lmin,
                      int lmax, bool adjoint, int precision, const void *ops, hipStream_t s);
 

@@ -8,6 +8,7 @@
 
 #include "fmm2d_internal.h"
 #include "m2l_bank.h"
+#include "m2l_hankel_bank.h"
 #include "m2l_mixed_bank.h"
 #include "m2l_pascal_bank.h"
 
@@ -286,6 +287,70 @@ __global__ void mixed_bank_kernel(unsigned char *bank) {
   }
 }
 
+// Hankel-form bank (m2l_hankel_bank.h), all in FP64 except the FP32 log rows.
+// G^_o[f] = sum_m g_m(d) exp(-2 pi i f m / N) with g_m(d) = m! rho^-m d^-(m+1),
+// d = -o; the angle of each term is reduced exactly, (f m) mod N.
+template <int P>
+__global__ void hankel_bank_kernel(unsigned char *bank) {
+  using B = HankelBank<P>;
+  constexpr int N = B::N;
+  const double rho = HankelCfg<P>::rho();
+  const double two_pi = 6.283185307179586476925286766559;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  const size_t i0 = blockIdx.x * size_t(blockDim.x) + threadIdx.x;
+  cd *ghat = reinterpret_cast<cd *>(bank + B::ghat_off);
+  for (size_t i = i0; i < size_t(kSlots) * N; i += stride) {
+    const int f = int(i % N), slot = int(i / N);
+    int ox, oy;
+    cd acc = {0.0, 0.0};
+    if (slot_used(slot, ox, oy)) {
+      const cd d = {double(-ox), double(-oy)};
+      const double den = d.re * d.re + d.im * d.im;
+      const cd dinv = {d.re / den, -d.im / den};
+      cd dp = dinv;      // d^-(m+1)
+      double c = 1.0;    // m! rho^-m
+      for (int m = 0; m <= 2 * P - 2; ++m) {
+        if (m > 0) {
+          c *= double(m) / rho;
+          dp = cmul(dp, dinv);
+        }
+        const double ang = -two_pi * double((f * m) % N) / double(N);
+        const cd w = {cos(ang), sin(ang)};
+        const cd t = cmul(dp, w);
+        acc.re += c * t.re;
+        acc.im += c * t.im;
+      }
+    }
+    ghat[i] = acc;
+  }
+  double *dr = reinterpret_cast<double *>(bank + B::dr_off);
+  double *dl = reinterpret_cast<double *>(bank + B::dl_off);
+  if (i0 == 0) {
+    double c = 1.0;  // rho^k / k!
+    for (int k = 0; k < P; ++k) {
+      if (k > 0) c *= rho / double(k);
+      dr[k] = c;
+      dl[k] = (k & 1) ? -c : c;
+    }
+  }
+  cd *tw = reinterpret_cast<cd *>(bank + B::tw_off);
+  for (size_t i = i0; i < size_t(N); i += stride) {
+    const double ang = -two_pi * double(i) / double(N);
+    tw[i] = {cos(ang), sin(ang)};
+  }
+  float *r = reinterpret_cast<float *>(bank + B::r_off);
+  for (size_t i = i0; i < size_t(kSlots) * P * 2; i += stride) {
+    const int ri = int(i % 2), k = int((i / 2) % P), slot = int(i / 2 / P);
+    int ox, oy;
+    float v = 0.f;
+    if (slot_used(slot, ox, oy)) {
+      const cd rv = log_row_entry(double(-ox), double(-oy), k);
+      v = float(ri ? rv.im : rv.re);
+    }
+    r[i] = v;
+  }
+}
+
 size_t mixed_bank_bytes(int p, int precision) {
   if (precision != FMM2D_BF16X3 && precision != FMM2D_F16X3) return 0;
   switch (p) {
@@ -319,10 +384,22 @@ size_t m2l_ops_bytes(int p, int precision) {
   if (!p_supported(p)) return 0;
   if (precision == FMM2D_F32) return f32_bank_bytes(p);
   if (precision == FMM2D_F32_PASCAL) return pascal_bank_bytes(p);
+  if (precision == FMM2D_F64_HANKEL) return hankel_bank_bytes(p);
   return mixed_bank_bytes(p, precision);
 }
 
 int launch_m2l_ops(int p, int precision, void *ops, hipStream_t s) {
+  if (precision == FMM2D_F64_HANKEL) {
+    unsigned char *bank = static_cast<unsigned char *>(ops);
+    dim3 grid(64), block(256);
+    switch (p) {
+      case 8: hipLaunchKernelGGL(hankel_bank_kernel<8>, grid, block, 0, s, bank); break;
+      case 12: hipLaunchKernelGGL(hankel_bank_kernel<12>, grid, block, 0, s, bank); break;
+      case 16: hipLaunchKernelGGL(hankel_bank_kernel<16>, grid, block, 0, s, bank); break;
+      case 20: hipLaunchKernelGGL(hankel_bank_kernel<20>, grid, block, 0, s, bank); break;
+    }
+    return check_launch("m2l Hankel-form operator bank");
+  }
   if (precision == FMM2D_F32_PASCAL) {
     float *bank = static_cast<float *>(ops);
     dim3 grid(512), block(256);

@@ -129,6 +129,27 @@ def test_split_precision_banks_are_built_for_every_order():
         assert rc == -5
 
 
+def test_hankel_bank_sizes_follow_its_layout():
+    """FMM2D_F64_HANKEL bank: 49 operator spectra of 2p complex doubles, the
+    two scalings (p doubles each), 2p twiddles and 49 log rows of p complex
+    floats, each section after the scalings aligned to 256 bytes."""
+    lib = _lib()
+
+    def up(x):
+        return (x + 255) // 256 * 256
+
+    for p in (8, 12, 16, 20):
+        n = 2 * p
+        tw = up(49 * n * 16 + 2 * p * 8)
+        r = up(tw + n * 16)
+        assert lib.fmm2d_m2l_operators_bytes(p, 4) == up(r + 49 * p * 8)
+    assert lib.fmm2d_m2l_operators_bytes(10, 4) == 0
+    need = lib.fmm2d_m2l_operators_bytes(20, 4)
+    assert lib.fmm2d_m2l(FAKE, ctypes.c_void_p(0x2000), None, 10, 20, 2, 10, 4, FAKE, need - 1, None) == -5
+    assert lib.fmm2d_m2l_backward(FAKE, None, ctypes.c_void_p(0x2000), 10, 20, 2, 10, 4, FAKE, need - 1,
+                                  None) == -5
+
+
 def test_fgt_rejects_bad_arguments_on_host():
     lib = _lib()
     f = ctypes.c_float
@@ -156,7 +177,7 @@ def test_pascal_form_banks_are_built_for_every_order():
     sizes = [lib.fmm2d_m2l_operators_bytes(p, 3) for p in (8, 12, 16, 20)]
     assert all(s > 0 for s in sizes) and sizes == sorted(sizes)
     assert lib.fmm2d_m2l_operators_bytes(10, 3) == 0
-    assert lib.fmm2d_m2l_operators_bytes(12, 4) == 0
+    assert lib.fmm2d_m2l_operators_bytes(12, 5) == 0
     need = lib.fmm2d_m2l_operators_bytes(12, 3)
     rc = lib.fmm2d_m2l(FAKE, ctypes.c_void_p(0x2000), None, 8, 12, 2, 8, 3, FAKE, need - 1, None)
     assert rc == -5
