@@ -550,6 +550,26 @@ def fgt_bench(name, seed, dev, steps, warmup, cpu=True, cpu_budget_s=12.0):
     return out
 
 
+def near_field_pairs(leaf_start, depth):
+    """Ordered source-target pairs (i != j) the near field evaluates: every
+    point of a leaf against every other point of the leaf and its 8
+    neighbours.  leaf_start holds the Morton-ordered leaf offsets (host)."""
+    import numpy as np
+    counts = np.diff(np.asarray(leaf_start, np.int64))
+    m = np.arange(counts.size, dtype=np.int64)
+    x = np.zeros_like(m)
+    y = np.zeros_like(m)
+    for bit in range(depth):
+        x |= ((m >> (2 * bit)) & 1) << bit
+        y |= ((m >> (2 * bit + 1)) & 1) << bit
+    side = 1 << depth
+    grid = np.zeros((side + 2, side + 2), np.int64)
+    grid[y + 1, x + 1] = counts
+    near = sum(grid[1 + dy:side + 1 + dy, 1 + dx:side + 1 + dx] for dy in (-1, 0, 1) for dx in (-1, 0, 1))
+    c = grid[1:side + 1, 1:side + 1]
+    return int(np.sum(c * near) - np.sum(c))
+
+
 def fmm_stage_times(name, prec_name, seed, dev, reps=5):
     """Per-stage times (ms, median of `reps`) of the whole FMM with every point
     as both source and target: tree build (with the sorted gathers), P2M, M2M,
@@ -618,6 +638,10 @@ def fmm_stage_times(name, prec_name, seed, dev, reps=5):
     out = {k: v for k, v in zip(names, med)}
     out["forward_total"] = sum(med[:7])
     out["backward_total"] = sum(med[7:])
+    pairs = near_field_pairs(ls.cpu().numpy(), depth)
+    out["p2p_pairs"] = pairs
+    out["p2p_pairs_per_s"] = pairs / (out["p2p"] * 1e-3)
+    out["p2p_T_pairs_per_s"] = pairs / (out["p2p_T"] * 1e-3)
     out["workload"] = name
     out["precision"] = prec_name
     return out

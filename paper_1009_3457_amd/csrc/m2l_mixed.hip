@@ -7,13 +7,13 @@
 // split product of m2l_mixed_bank.h: FP32 inputs are split into 16-bit hi and
 // lo parts once, while staged, and every product accumulates in FP32.
 //
-// Work decomposition: 16x16 target tiles (deepest level first), one
-// four-wave workgroup per tile, two workgroups per compute unit.  Wave c owns
-// child class c: its 64 target boxes form 4 column blocks of 16 (N tiles),
+// Work decomposition: 16x16 target tiles (deepest level first); one
+// persistent workgroup per compute unit (registers allow no second) with four
+// compute waves and four loader waves.  Compute wave c owns child class c: its 64 target boxes form 4 column blocks of 16 (N tiles),
 // so each operator fragment it fetches serves 4 products.  The 20x20 source
 // block around the tile (halo 2) is loaded from HBM, split, and stored in LDS
-// once per tile; while one workgroup stages, the other's products keep the
-// matrix cores busy.  Operator fragments stream from the L2-resident bank
+// once per tile by the loader waves, into the second of two buffers while the
+// compute waves' products run on the first.  Operator fragments stream from the L2-resident bank
 // two offsets ahead (they do not depend on the tile, so the stream runs on
 // across tiles).  Persistent workgroups take tiles in rounds; within a round
 // the workgroups of one XCD take a contiguous run of tiles, so the halos that
@@ -46,7 +46,13 @@ constexpr int kMShift = 4;                   // tiles of 16 x 16 boxes
 constexpr int kMTile = 1 << kMShift;
 constexpr int kMReg = kMTile + 2 * kHalo;    // staged source block side (20)
 constexpr int kMRegBoxes = kMReg * kMReg;    // 400
-constexpr int kMPlane = kMRegBoxes + 1;      // 16-byte units per plane (+1: planes start on different banks)
+// 16-byte units per plane.  ds_read_b128 serves 32 lanes (two lane groups
+// g of the B fragment) per pass over 128 four-byte banks, i.e. 32 units; a
+// lane group reads 16 units that are contiguous modulo 32, so two planes
+// whose indices differ by an odd number fall on disjoint banks when the
+// plane stride is 16 modulo 32 (400 = 12 * 32 + 16).
+constexpr int kMPlane = kMRegBoxes;
+static_assert(kMPlane % 32 == 16, "planes an odd number apart must fall on disjoint banks");
 constexpr int kMRow = 40;                    // units per row of same-class boxes: 4 classes x 10
 
 template <int P>
@@ -273,13 +279,19 @@ __device__ __forceinline__ void mixed_compute(LdsMix<P, ADJ> &sm, float2 *__rest
 
   // LDS byte address (within a buffer) of this lane's B chunk for k-step ks
   // at window (0, 0); per offset and N tile only an immediate is added
+  // B plane of lane group gg at k-step ks; a padding chunk (A is 0 there)
+  // reads any staged plane, chosen an odd number of planes from its pass
+  // partner's (gg - 1) so the two share no bank
+  auto bplane = [](int ks, int gg) {
+    const int q = 4 * ks + gg, seg = q / NPL;
+    if (seg < 3) return ((seg == 1) ? NPL : 0) + q % NPL;
+    const int qp = q - 1, segp = qp / NPL;
+    if ((gg & 1) && segp < 3) return (((segp == 1) ? NPL : 0) + qp % NPL) ^ 1;
+    return 0;
+  };
   int abase[KS];
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
-    const int q = 4 * ks + g, seg = q / NPL;
-    const int pl = seg >= 3 ? 0 : ((seg == 1) ? NPL : 0) + q % NPL;  // zero chunk: any finite data (A is 0)
-    abase[ks] = (pl * kMPlane + kMRow * (j >> 3) + (j & 7)) * 16;
-  }
+  for (int ks = 0; ks < KS; ++ks) abase[ks] = (bplane(ks, g) * kMPlane + kMRow * (j >> 3) + (j & 7)) * 16;
   auto bimm = [&](int i, int nt) {  // compile-time after unrolling; this wave's N tile nt is NT H + nt
     const int ox = sx * kOff00.ox[i], oy = sy * kOff00.oy[i];
     return (2 * kMRow * (NT * H + nt) + kMRow * ((CY + kHalo + oy) >> 1) + 10 * (((CX + ox) & 1) + 2 * ((CY + oy) & 1)) +

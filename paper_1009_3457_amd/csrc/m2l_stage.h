@@ -23,15 +23,19 @@ struct StageCfg {
 // fragment of lane (kk, j) for one offset is NE units (2S floats: Re, Im of
 // k = S kk + s) of one box; the 16 lanes of a k-group read a 4x4 window of
 // same-class boxes (stride 2 in the region).  Boxes are therefore stored by
-// class: unit = kRow v' + 6 class + u' with (u', v') = (u, v) / 2, and
-// kRow = 28 = 12 (mod 16) makes the 16 units of any 4x4 window fall on 16
-// distinct 16-byte bank groups, so the reads are free of bank conflicts.
+// class: unit = kRow v' + 6 class + u' with (u', v') = (u, v) / 2.
+// A 16-byte LDS read serves 32 lanes (two k-groups) per pass over 128
+// four-byte banks, i.e. 32 units.  kRow makes the 16 units of a window
+// distinct modulo 32, and the plane stride puts the next k-group's window
+// (NE kPlane units on) on the other 16 residues, so the reads are free of
+// bank conflicts: kRow 28, kPlane 168 for NE = 2; kRow 24, kPlane 148 for
+// NE = 1 and 3 (found by search over the strides that fit the block).
 template <int P>
 struct XLayout {
   static constexpr int S = P / 4;
   static constexpr int NE = (2 * S + 3) / 4;  // units per (k-group, box) record
-  static constexpr int kRow = 28;             // 4 classes x 6 + 4 spare units
-  static constexpr int kPlane = 6 * kRow;     // units per (k-group, unit index)
+  static constexpr int kRow = NE == 2 ? 28 : 24;        // 4 classes x 6 (+ 4 spare units)
+  static constexpr int kPlane = NE == 2 ? 6 * kRow : 148;  // units per (k-group, unit index)
   static constexpr int kFloats = 4 * NE * kPlane * 4;
   __device__ static int unit(int kk, int e, int u, int v) {  // u, v in [0, 12)
     return (kk * NE + e) * kPlane + kRow * (v >> 1) + 6 * ((u & 1) + 2 * (v & 1)) + (u >> 1);
