@@ -86,7 +86,8 @@ typedef enum fmm2d_precision {
                           /*   (entries depend on n + k between two diagonals): the    */
                           /*   list's translations summed as spectra of length 2p,     */
                           /*   27 complex multiply-adds per target and frequency;      */
-                          /*   accumulation in FP64, not FP32                          */
+                          /*   L~ accumulated in FP64 on the vector ALUs; the log row  */
+                          /*   b (and its transpose) in FP32, in a pass of its own     */
 } fmm2d_precision;
 
 /* ----------------------------------------------------------- queries ---- */

@@ -37,6 +37,8 @@ class M2LFunction(torch.autograd.Function):
 
 
 def m2l(M, depth: int, p: int, lmin: int = 2, lmax: int | None = None, precision="f32"):
+    """Differentiable M2L of the scaled multipoles M (levels lmin..lmax);
+    precision as in potential()."""
     prec = B.PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     lmax = depth if lmax is None else lmax
     return M2LFunction.apply(M, depth, p, lmin, lmax, prec)
@@ -141,6 +143,8 @@ def potential(xy, q, targets=None, depth: int = 8, p: int = 12, precision="f32")
     targets (default: the sources, with self-interaction excluded), by the FMM.
 
     xy [n, 2] and q [n] float32 on the GPU; returns complex64 (phi, field).
+    precision selects the M2L form: "f32" (Gauss), "f32_pascal", "bf16x3",
+    "f16x3" or "f64_hankel" (the keys of PRECISIONS), or its integer code.
     Gradients (at a frozen tree) flow to q and xy, and to the targets' positions
     for a loss on phi.  With targets=None the sources are also the evaluation
     points, so xy's gradient holds both the source-side and the target-side
