@@ -15,7 +15,9 @@ Prints one JSON line with:
   * translations/s, using the exact, boundary-truncated count;
   * Gop/s, at 8p^2 flops per translation;
   * the roofline of the M2L kernel, timed with HIP events on its stream
-    (mean over the timed launches), priced at the flops the launched form
+    (mean over the timed launches; the default 2000 untimed launches before
+    them, about 50 ms of load, let the shader clock settle, which takes tens
+    of milliseconds from an idle GPU), priced at the flops the launched form
     performs (Pascal form 4p^2 + 14p, +4p + 8 with b; Gauss form 6p^2 + p,
     +6p + 2; split precision 24p^2, +24p), and as `effective_frac` at the
     dense operator's 8p^2 (+8p);
@@ -650,8 +652,8 @@ def fmm_stage_times(name, prec_name, seed, dev, reps=5):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["f32", "f32_pascal", "bf16x3", "f16x3", "f64_hankel"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
