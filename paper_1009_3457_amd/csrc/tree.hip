@@ -260,12 +260,37 @@ __global__ void gather_kernel(const float *__restrict__ src, const int32_t *__re
   else dst[e] = src[int64_t(perm[i]) * width + c];
 }
 
+// Rows of 1, 2 or 4 floats (charges, positions, complex values; pairs of
+// complex values) move as one vector access per row: no index division, and
+// one load of perm per row.
+template <typename V>
+__global__ void gather_rows_kernel(const V *__restrict__ src, const int32_t *__restrict__ perm, int64_t n,
+                                   V *__restrict__ dst, bool scatter) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j = perm[i];
+  if (scatter) dst[j] = src[i];
+  else dst[i] = src[j];
+}
+
+template <typename V>
+void launch_rows(const float *src, const int32_t *perm, int64_t n, float *dst, bool scatter, hipStream_t s) {
+  hipLaunchKernelGGL(gather_rows_kernel<V>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<const V *>(src), perm, n, reinterpret_cast<V *>(dst), scatter);
+}
+
 int launch_gather(const float *src, const int32_t *perm, int64_t n, int width, float *dst, bool scatter,
                   hipStream_t s) {
   if (n == 0) return FMM2D_OK;
-  const int64_t tot = n * width;
-  hipLaunchKernelGGL(gather_kernel, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, s, src, perm, n, width, dst,
-                     scatter);
+  const uintptr_t align = reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst);
+  if (width == 1) launch_rows<float>(src, perm, n, dst, scatter, s);
+  else if (width == 2 && align % 8 == 0) launch_rows<float2>(src, perm, n, dst, scatter, s);
+  else if (width == 4 && align % 16 == 0) launch_rows<float4>(src, perm, n, dst, scatter, s);
+  else {
+    const int64_t tot = n * width;
+    hipLaunchKernelGGL(gather_kernel, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, s, src, perm, n, width, dst,
+                       scatter);
+  }
   return check_launch(scatter ? "scatter" : "gather");
 }
 

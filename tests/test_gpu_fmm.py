@@ -42,6 +42,28 @@ def test_build_tree_bit_exact(P, n, depth, kind):
     assert np.array_equal(ls.cpu().numpy(), ls_r)
 
 
+@pytest.mark.parametrize("shape,dtype,offset", [((1000,), "float32", 0), ((1000, 2), "float32", 0),
+                                                ((1000, 2), "float32", 1), ((1000, 2), "complex64", 0),
+                                                ((1000, 3), "float32", 0), ((1000,), "complex64", 1)])
+def test_gather_scatter_are_exact_permutations(P, shape, dtype, offset):
+    """Rows of 1, 2 and 4 floats take the vector path, others (and a
+    misaligned view) the element path; both move every bit exactly."""
+    import torch
+    g = np.random.Generator(np.random.PCG64(55))
+    n = shape[0]
+    perm = torch.from_numpy(g.permutation(n).astype(np.int32)).cuda()
+    count = int(np.prod(shape))
+    flat = torch.from_numpy(g.standard_normal(count + 1).astype(np.float32)).cuda()
+    if dtype == "complex64":
+        flat = torch.from_numpy((g.standard_normal(count + 1) + 1j * g.standard_normal(count + 1))
+                                .astype(np.complex64)).cuda()
+    src = flat[offset:offset + count].view(shape)
+    out = P.gather(src, perm)
+    assert torch.equal(out, src[perm.long()])
+    back = P.scatter(out, perm)
+    assert torch.equal(back, src)
+
+
 def test_build_tree_rejects_points_outside(P):
     xy = sy.uniform(100, 1)
     xy[17] = (0.5, 1.25)
