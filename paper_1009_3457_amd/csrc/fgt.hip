@@ -169,7 +169,12 @@ template <int P>
 __global__ __launch_bounds__(256) void fgt_eval_kernel(const float2 *__restrict__ txy, int64_t nt, int depth,
                                                        float inv_s, int K, const float *__restrict__ A,
                                                        float *__restrict__ G) {
-  const int64_t t0 = (blockIdx.x * int64_t(4) + (threadIdx.x >> 6)) * 64;
+  // Blocks are dispatched to the 8 XCDs in turn (b mod 8).  Each XCD takes a
+  // contiguous eighth of the (box-ordered) targets, so the coefficient boxes
+  // that neighbouring waves visit are fetched once into that XCD's L2.
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  const int64_t lb = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int64_t t0 = (lb * 4 + (threadIdx.x >> 6)) * 64;
   if (t0 >= nt) return;  // whole wave
   const int lane = threadIdx.x & 63;
   const int64_t t = t0 + lane;
