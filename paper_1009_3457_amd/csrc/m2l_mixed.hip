@@ -9,11 +9,16 @@
 //
 // Work decomposition: 16x16 target tiles (deepest level first); one
 // persistent workgroup per compute unit (registers allow no second) with four
-// compute waves and four loader waves.  Compute wave c owns child class c: its 64 target boxes form 4 column blocks of 16 (N tiles),
-// so each operator fragment it fetches serves 4 products.  The 20x20 source
-// block around the tile (halo 2) is loaded from HBM, split, and stored in LDS
-// once per tile by the loader waves, into the second of two buffers while the
-// compute waves' products run on the first.  Operator fragments stream from the L2-resident bank
+// compute waves and four loader waves.  Compute wave c owns child class c:
+// its 64 target boxes form 4 column blocks of 16 (N tiles), so each operator
+// fragment it fetches serves 4 products.  The 20x20 source block around the
+// tile (halo 2) is loaded from HBM, split, and stored in LDS once per tile by
+// the loader waves, into the second of two buffers while the compute waves'
+// products run on the first.  A tree with fewer tiles than two per compute
+// unit (2^20 points at depth 8 has 342) would leave most units idle in the
+// second round, so there the four compute waves stage their own tile into a
+// single buffer and two such workgroups share a compute unit: one's staging
+// overlaps the other's products.  Operator fragments stream from the L2-resident bank
 // two offsets ahead (they do not depend on the tile, so the stream runs on
 // across tiles).  Persistent workgroups take tiles in rounds; within a round
 // the workgroups of one XCD take a contiguous run of tiles, so the halos that
@@ -55,15 +60,23 @@ constexpr int kMPlane = kMRegBoxes;
 static_assert(kMPlane % 32 == 16, "planes an odd number apart must fall on disjoint banks");
 constexpr int kMRow = 40;                    // units per row of same-class boxes: 4 classes x 10
 
-template <int P>
+// SELF: the compute waves stage their own tiles (one buffer, no loader
+// waves), so a workgroup needs half the waves and LDS and two fit per compute
+// unit; used when the tiles are too few to fill two rounds of one workgroup
+// per compute unit.
+template <int P, bool SELF = false>
 struct MixK {
   using C = MixCfg<P>;
   static constexpr int kHalves = 1;  // compute waves per class (2 doubles the operator fetches: slower)
   static constexpr int NT = 4 / kHalves;  // N tiles (16 boxes each) per compute wave; a class has 4
   static constexpr int kCompute = 4 * kHalves;  // compute waves: kHalves per class
-  static constexpr int kLoaders = 4;            // loader waves: stage the next tile's source block
+  static constexpr int kLoaders = SELF ? 0 : 4;  // loader waves: stage the next tile's source block
   static constexpr int kThreads = 64 * (kCompute + kLoaders);
-  static constexpr int kLThreads = 64 * kLoaders;
+  static constexpr int kStageWaves = 4;           // waves that stage a block (loaders, or the compute waves)
+  static constexpr int kLThreads = 64 * kStageWaves;
+  static constexpr int kBuffers = SELF ? 1 : 2;
+  static constexpr int kWgPerCu = SELF ? 2 : 1;
+  static_assert(!SELF || kCompute == kStageWaves, "self-staging needs one staging slot per compute wave");
   static constexpr int kItems = (kMRegBoxes * C::NPL + kLThreads - 1) / kLThreads;  // staging items per loader thread
   static constexpr int kPlanes = 2 * C::NPL;                                        // hi chunks, lo chunks
   static constexpr int kPlaneUnits = kPlanes * kMPlane;
@@ -84,12 +97,13 @@ __device__ constexpr int munit(int pl, int u, int v) {
 
 // Two staging buffers: the loader waves fill one while the compute waves
 // read the other.
-template <int P, bool ADJ>
+template <int P, bool ADJ, bool SELF = false>
 struct LdsMix {
-  u32x4_t x[2][MixK<P>::kPlaneUnits];
-  float2 gb[2][ADJ ? kMRegBoxes + 1 : 1];  // entry kMRegBoxes stays zero
-  float wmax[MixK<P>::kLoaders];
-  int scale[2];  // FP16x3: the block is stored times 2^scale
+  static constexpr int NB = MixK<P, SELF>::kBuffers;
+  u32x4_t x[NB][MixK<P, SELF>::kPlaneUnits];
+  float2 gb[NB][ADJ ? kMRegBoxes + 1 : 1];  // entry kMRegBoxes stays zero
+  float wmax[MixK<P, SELF>::kStageWaves];
+  int scale[NB];  // FP16x3: the block is stored times 2^scale
 };
 
 template <int PREC>
@@ -161,11 +175,11 @@ __device__ inline int round_tile(int r, int b, int G) {
 // store.  FP16x3 runs one workgroup barrier between finding the block's
 // largest magnitude and storing (the compute waves run the matching one
 // inside their offset loop); `active` false only takes that barrier.
-template <int P, int PREC, bool ADJ>
-__device__ __forceinline__ void mixed_stage(LdsMix<P, ADJ> &sm, int buf, bool active, const MGeo &geo,
+template <int P, int PREC, bool ADJ, bool SELF>
+__device__ __forceinline__ void mixed_stage(LdsMix<P, ADJ, SELF> &sm, int buf, bool active, const MGeo &geo,
                                             const float2 *__restrict__ X, const float2 *__restrict__ gbin, int ltid) {
   using C = MixCfg<P>;
-  using K = MixK<P>;
+  using K = MixK<P, SELF>;
   constexpr int NPL = C::NPL;
   constexpr bool kF16 = (PREC == FMM2D_F16X3);
   float4 v[K::kItems][2];
@@ -211,7 +225,7 @@ __device__ __forceinline__ void mixed_stage(LdsMix<P, ADJ> &sm, int buf, bool ac
     if ((ltid & 63) == 0) sm.wmax[ltid >> 6] = m;
     __syncthreads();  // the mid-tile barrier
 #pragma unroll
-    for (int w = 0; w < K::kLoaders; ++w) m = fmaxf(m, sm.wmax[w]);
+    for (int w = 0; w < K::kStageWaves; ++w) m = fmaxf(m, sm.wmax[w]);
     sc = (m > 0.f) ? 14 - ilogbf(m) : 0;
     if (ltid == 0 && active) sm.scale[buf] = sc;
   }
@@ -242,25 +256,25 @@ __device__ __forceinline__ void mixed_stage(LdsMix<P, ADJ> &sm, int buf, bool ac
 }
 
 template <int P, int PREC, bool ADJ>
-__device__ __forceinline__ void mixed_loader(LdsMix<P, ADJ> &sm, const float2 *__restrict__ X,
+__device__ __forceinline__ void mixed_loader(LdsMix<P, ADJ, false> &sm, const float2 *__restrict__ X,
                                              const float2 *__restrict__ gbin, const TileMap &map, int ntiles,
                                              int ltid) {
   const int G = int(gridDim.x), b = int(blockIdx.x);
   for (int r = 0, t = round_tile(0, b, G); t < ntiles; t = round_tile(++r, b, G)) {
     const int tn = round_tile(r + 1, b, G);
     const bool has_next = tn < ntiles;
-    mixed_stage<P, PREC, ADJ>(sm, (r + 1) & 1, has_next, mgeo(map, has_next ? tn : t), X, gbin, ltid);
+    mixed_stage<P, PREC, ADJ, false>(sm, (r + 1) & 1, has_next, mgeo(map, has_next ? tn : t), X, gbin, ltid);
     __syncthreads();  // end of round r
   }
 }
 
 // ----------------------------------------------------------- compute waves --
-template <int P, int PREC, bool ADJ, int CX, int CY, int H>
-__device__ __forceinline__ void mixed_compute(LdsMix<P, ADJ> &sm, float2 *__restrict__ Y, float2 *__restrict__ bout,
+template <int P, int PREC, bool ADJ, bool SELF, int CX, int CY, int H>
+__device__ __forceinline__ void mixed_compute(LdsMix<P, ADJ, SELF> &sm, float2 *__restrict__ Y, float2 *__restrict__ bout,
                                               const unsigned char *__restrict__ bank, const TileMap &map, int ntiles,
-                                              int tid) {
+                                              int tid, const float2 *__restrict__ X, const float2 *__restrict__ gbin) {
   using C = MixCfg<P>;
-  using K = MixK<P>;
+  using K = MixK<P, SELF>;
   using B = MixedBank<P>;
   constexpr int MT = C::MT, KS = C::KS, NT = K::NT, NPL = C::NPL, R = C::R;
   constexpr int kApf = K::kApf, kRing = kApf + 1;
@@ -333,14 +347,20 @@ __device__ __forceinline__ void mixed_compute(LdsMix<P, ADJ> &sm, float2 *__rest
   if (kCarryA)
 #pragma unroll
     for (int i = 0; i < kApf; ++i) load_a(i, i);
-  if (kF16) __syncthreads();  // the prologue's mid-tile barrier (loader waves stage tile 0)
-  __syncthreads();            // tile 0 is staged
+  if (!SELF) {
+    if (kF16) __syncthreads();  // the prologue's mid-tile barrier (loader waves stage tile 0)
+    __syncthreads();            // tile 0 is staged
+  }
 
   const float ln2 = 0.69314718055994530942f;
   const int G = int(gridDim.x), bidx = int(blockIdx.x);
   for (int r = 0, t = round_tile(0, bidx, G); t < ntiles; t = round_tile(++r, bidx, G)) {
     const MGeo geo = mgeo(map, t);
-    const int buf = r & 1;
+    const int buf = SELF ? 0 : (r & 1);
+    if constexpr (SELF) {  // the four compute waves stage this tile (with FP16x3 the block maximum's barrier is inside)
+      mixed_stage<P, PREC, ADJ, true>(sm, 0, true, geo, X, gbin, tid);
+      __syncthreads();  // the tile is staged
+    }
     const char *xb = reinterpret_cast<const char *>(sm.x[buf]);
     auto lds16 = [&](int byte_off) { return *reinterpret_cast<const u32x4_t *>(xb + byte_off); };
     const int sc = kF16 ? sm.scale[buf] : 0;
@@ -401,7 +421,7 @@ __device__ __forceinline__ void mixed_compute(LdsMix<P, ADJ> &sm, float2 *__rest
           __builtin_amdgcn_sched_group_barrier(0x008, MT * NT * KS, 0);  // the rest of the products
         }
         __builtin_amdgcn_sched_barrier(0);
-        if (kF16 && i == K::kMid) __syncthreads();  // matches the loader waves' mid-tile barrier
+        if (kF16 && !SELF && i == K::kMid) __syncthreads();  // matches the loader waves' mid-tile barrier
       }
     } else {
       // source fragments of one N tile, one N tile ahead (fewer registers)
@@ -429,7 +449,7 @@ __device__ __forceinline__ void mixed_compute(LdsMix<P, ADJ> &sm, float2 *__rest
               acc[mt][nt] = mfma16<PREC>(A[ap][mt][C::a_src(ks)], Bn[pos][C::b_src(ks)], acc[mt][nt]);
           __builtin_amdgcn_sched_barrier(0);
         }
-        if (kF16 && i == K::kMid) __syncthreads();  // matches the loader waves' mid-tile barrier
+        if (kF16 && !SELF && i == K::kMid) __syncthreads();  // matches the loader waves' mid-tile barrier
       }
     }
     if (kCarryA && 27 % kRing != 0) {
@@ -523,69 +543,83 @@ __device__ __forceinline__ void mixed_compute(LdsMix<P, ADJ> &sm, float2 *__rest
         }
       }
     }
-    __syncthreads();  // end of round r: buffer r & 1 is free, the next tile is staged
+    __syncthreads();  // end of round r: buffer r & 1 is free, the next tile is staged (SELF: the buffer is free)
   }
 }
 
-template <int P, int PREC, bool ADJ>
-__global__ __launch_bounds__(MixK<P>::kThreads, 1) void m2l_mixed_kernel(const float2 *__restrict__ X,
+template <int P, int PREC, bool ADJ, bool SELF>
+__global__ __launch_bounds__((MixK<P, SELF>::kThreads)) __attribute__((amdgpu_waves_per_eu(MixK<P, SELF>::kWgPerCu)))
+void m2l_mixed_kernel(const float2 *__restrict__ X,
                                                                          const float2 *__restrict__ gbin,
                                                                          float2 *__restrict__ Y,
                                                                          float2 *__restrict__ bout,
                                                                          const unsigned char *__restrict__ bank,
                                                                          TileMap map, int ntiles) {
-  using K = MixK<P>;
-  __shared__ __attribute__((aligned(16))) LdsMix<P, ADJ> sm;
+  using K = MixK<P, SELF>;
+  __shared__ __attribute__((aligned(16))) LdsMix<P, ADJ, SELF> sm;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: the role lives in SGPRs
-  if (ADJ && tid == 0) {
-    sm.gb[0][kMRegBoxes] = make_float2(0.f, 0.f);
-    sm.gb[1][kMRegBoxes] = make_float2(0.f, 0.f);
-  }
+  if (ADJ && tid == 0)
+    for (int nb = 0; nb < K::kBuffers; ++nb) sm.gb[nb][kMRegBoxes] = make_float2(0.f, 0.f);
+  if (SELF) __syncthreads();  // the zero slot is written before any wave reads it
   // Both roles run the same number of workgroup barriers: per round one at
   // its end, and with FP16x3 one more in its middle (and in the prologue).
-  if (wave >= K::kCompute) {
-    const int ltid = tid - 64 * K::kCompute;
-    const int G = int(gridDim.x), b = int(blockIdx.x);
-    const int t0 = round_tile(0, b, G);
-    mixed_stage<P, PREC, ADJ>(sm, 0, t0 < ntiles, mgeo(map, t0 < ntiles ? t0 : 0), X, gbin, ltid);
-    __syncthreads();  // tile 0 is staged
-    mixed_loader<P, PREC, ADJ>(sm, X, gbin, map, ntiles, ltid);
-    return;
+  if constexpr (!SELF) {
+    if (wave >= K::kCompute) {
+      const int ltid = tid - 64 * K::kCompute;
+      const int G = int(gridDim.x), b = int(blockIdx.x);
+      const int t0 = round_tile(0, b, G);
+      mixed_stage<P, PREC, ADJ, false>(sm, 0, t0 < ntiles, mgeo(map, t0 < ntiles ? t0 : 0), X, gbin, ltid);
+      __syncthreads();  // tile 0 is staged
+      mixed_loader<P, PREC, ADJ>(sm, X, gbin, map, ntiles, ltid);
+      return;
+    }
   }
   // compute wave w: class w mod 4, N tiles of half w / 4
   switch (wave) {
-    case 0: mixed_compute<P, PREC, ADJ, 0, 0, 0>(sm, Y, bout, bank, map, ntiles, tid); break;
-    case 1: mixed_compute<P, PREC, ADJ, 1, 0, 0>(sm, Y, bout, bank, map, ntiles, tid); break;
-    case 2: mixed_compute<P, PREC, ADJ, 0, 1, 0>(sm, Y, bout, bank, map, ntiles, tid); break;
-    case 3: mixed_compute<P, PREC, ADJ, 1, 1, 0>(sm, Y, bout, bank, map, ntiles, tid); break;
+    case 0: mixed_compute<P, PREC, ADJ, SELF, 0, 0, 0>(sm, Y, bout, bank, map, ntiles, tid, X, gbin); break;
+    case 1: mixed_compute<P, PREC, ADJ, SELF, 1, 0, 0>(sm, Y, bout, bank, map, ntiles, tid, X, gbin); break;
+    case 2: mixed_compute<P, PREC, ADJ, SELF, 0, 1, 0>(sm, Y, bout, bank, map, ntiles, tid, X, gbin); break;
+    case 3: mixed_compute<P, PREC, ADJ, SELF, 1, 1, 0>(sm, Y, bout, bank, map, ntiles, tid, X, gbin); break;
     default:
       if constexpr (K::kHalves == 2) {
         switch (wave) {
-          case 4: mixed_compute<P, PREC, ADJ, 0, 0, 1>(sm, Y, bout, bank, map, ntiles, tid); break;
-          case 5: mixed_compute<P, PREC, ADJ, 1, 0, 1>(sm, Y, bout, bank, map, ntiles, tid); break;
-          case 6: mixed_compute<P, PREC, ADJ, 0, 1, 1>(sm, Y, bout, bank, map, ntiles, tid); break;
-          default: mixed_compute<P, PREC, ADJ, 1, 1, 1>(sm, Y, bout, bank, map, ntiles, tid); break;
+          case 4: mixed_compute<P, PREC, ADJ, SELF, 0, 0, 1>(sm, Y, bout, bank, map, ntiles, tid, X, gbin); break;
+          case 5: mixed_compute<P, PREC, ADJ, SELF, 1, 0, 1>(sm, Y, bout, bank, map, ntiles, tid, X, gbin); break;
+          case 6: mixed_compute<P, PREC, ADJ, SELF, 0, 1, 1>(sm, Y, bout, bank, map, ntiles, tid, X, gbin); break;
+          default: mixed_compute<P, PREC, ADJ, SELF, 1, 1, 1>(sm, Y, bout, bank, map, ntiles, tid, X, gbin); break;
         }
       }
       break;
   }
 }
 
-template <int P, int PREC>
-void launch_pp(const float *M, const float *gb_in, float *L, float *b, const TileMap &map, int ntiles, bool adjoint,
-               const void *ops, hipStream_t s) {
-  const int slots = num_cus();  // one workgroup per compute unit
+template <int P, int PREC, bool SELF>
+void launch_self(const float *M, const float *gb_in, float *L, float *b, const TileMap &map, int ntiles, bool adjoint,
+                 const void *ops, hipStream_t s) {
+  using K = MixK<P, SELF>;
+  const int slots = K::kWgPerCu * num_cus();
   const int grid = ntiles < slots ? ntiles : slots;
   const float2 *X = reinterpret_cast<const float2 *>(M);
   float2 *Y = reinterpret_cast<float2 *>(L);
   const unsigned char *bank = static_cast<const unsigned char *>(ops);
   if (adjoint)
-    hipLaunchKernelGGL((m2l_mixed_kernel<P, PREC, true>), dim3(grid), dim3(MixK<P>::kThreads), 0, s, X,
+    hipLaunchKernelGGL((m2l_mixed_kernel<P, PREC, true, SELF>), dim3(grid), dim3(K::kThreads), 0, s, X,
                        reinterpret_cast<const float2 *>(gb_in), Y, nullptr, bank, map, ntiles);
   else
-    hipLaunchKernelGGL((m2l_mixed_kernel<P, PREC, false>), dim3(grid), dim3(MixK<P>::kThreads), 0, s, X, nullptr, Y,
+    hipLaunchKernelGGL((m2l_mixed_kernel<P, PREC, false, SELF>), dim3(grid), dim3(K::kThreads), 0, s, X, nullptr, Y,
                        reinterpret_cast<float2 *>(b), bank, map, ntiles);
+}
+
+// Self-staging workgroups, two per compute unit, when the tiles would not fill
+// two rounds of one loader-backed workgroup per compute unit.
+template <int P, int PREC>
+void launch_pp(const float *M, const float *gb_in, float *L, float *b, const TileMap &map, int ntiles, bool adjoint,
+               const void *ops, hipStream_t s) {
+  if (ntiles < 2 * num_cus())
+    launch_self<P, PREC, true>(M, gb_in, L, b, map, ntiles, adjoint, ops, s);
+  else
+    launch_self<P, PREC, false>(M, gb_in, L, b, map, ntiles, adjoint, ops, s);
 }
 
 template <int PREC>
