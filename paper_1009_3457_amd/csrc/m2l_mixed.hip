@@ -163,9 +163,12 @@ __device__ inline MGeo mgeo(const TileMap &map, int t) {
 }
 
 // Tile of workgroup b in round r.  Workgroups are dispatched to the 8 XCDs
-// in turn (b mod 8); each XCD's workgroups take a contiguous run of G/8 tiles.
+// in turn (b mod 8); each XCD's workgroups take a contiguous run of tiles:
+// XCD x holds G/8 workgroups, one more when x < G mod 8, and its run starts
+// after those of XCDs 0..x-1 (a permutation of 0..G-1 for every G).
 __device__ inline int round_tile(int r, int b, int G) {
-  const int pos = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  const int x = b % 8, q = G / 8, rem = G % 8;
+  const int pos = x * q + (x < rem ? x : rem) + b / 8;
   return r * G + pos;
 }
 
