@@ -17,12 +17,13 @@
 // products run on the first.  A tree with fewer tiles than two per compute
 // unit (2^20 points at depth 8 has 342) would leave most units idle in the
 // second round, so there the four compute waves stage their own tile into a
-// single buffer and two such workgroups share a compute unit: one's staging
-// overlaps the other's products.  Operator fragments stream from the L2-resident bank
-// two offsets ahead (they do not depend on the tile, so the stream runs on
-// across tiles).  Persistent workgroups take tiles in rounds; within a round
-// the workgroups of one XCD take a contiguous run of tiles, so the halos that
-// neighbouring tiles share are found in that XCD's L2.
+// single buffer, and with half the waves and LDS two such workgroups share a
+// compute unit: every tile runs in the first round.  Operator fragments
+// stream from the L2-resident bank two offsets ahead (they do not depend on
+// the tile, so the stream runs on across tiles).  Persistent workgroups take
+// tiles in rounds; within a round the workgroups of one XCD take a contiguous
+// run of tiles, so the halos that neighbouring tiles share are found in that
+// XCD's L2.
 //
 // FP16 has a narrow exponent range, so for FP16x3 each tile's source block
 // (and gb) is scaled by one power of two chosen from its largest magnitude
@@ -95,8 +96,8 @@ __device__ constexpr int munit(int pl, int u, int v) {
   return pl * kMPlane + kMRow * (v >> 1) + 10 * ((u & 1) + 2 * (v & 1)) + (u >> 1);
 }
 
-// Two staging buffers: the loader waves fill one while the compute waves
-// read the other.
+// Staging buffers: two, the loader waves filling one while the compute waves
+// read the other; one for self-staging workgroups.
 template <int P, bool ADJ, bool SELF = false>
 struct LdsMix {
   static constexpr int NB = MixK<P, SELF>::kBuffers;
@@ -552,12 +553,8 @@ __device__ __forceinline__ void mixed_compute(LdsMix<P, ADJ, SELF> &sm, float2 *
 
 template <int P, int PREC, bool ADJ, bool SELF>
 __global__ __launch_bounds__((MixK<P, SELF>::kThreads)) __attribute__((amdgpu_waves_per_eu(MixK<P, SELF>::kWgPerCu)))
-void m2l_mixed_kernel(const float2 *__restrict__ X,
-                                                                         const float2 *__restrict__ gbin,
-                                                                         float2 *__restrict__ Y,
-                                                                         float2 *__restrict__ bout,
-                                                                         const unsigned char *__restrict__ bank,
-                                                                         TileMap map, int ntiles) {
+void m2l_mixed_kernel(const float2 *__restrict__ X, const float2 *__restrict__ gbin, float2 *__restrict__ Y,
+                      float2 *__restrict__ bout, const unsigned char *__restrict__ bank, TileMap map, int ntiles) {
   using K = MixK<P, SELF>;
   __shared__ __attribute__((aligned(16))) LdsMix<P, ADJ, SELF> sm;
   const int tid = threadIdx.x;
