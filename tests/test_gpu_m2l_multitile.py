@@ -9,9 +9,11 @@ oracle through the C ABI:
   * the 2^20-point, depth-8, p = 12 workload (the benchmark's), every box of
     every level, in all four precisions.
 
-The split-precision kernel takes self-staging workgroups (two per compute
-unit, one tile each) below two tiles per compute unit: the depth-8 case runs
-that path and the depth-9 and 10 cases the loader-backed one.
+The split-precision kernel runs self-staging workgroups (two per compute
+unit) for the adjoint at every size and for the forward map below two tiles
+per compute unit: the depth-8 forward case takes one tile per workgroup, the
+depth-9 and 10 adjoint cases several tiles per self-staging workgroup, and the
+depth-9 forward case the loader-backed workgroups.
 
 Tolerances (relative Frobenius error per level): FP32 forms 1e-5, split
 precision 1e-4.
