@@ -308,7 +308,21 @@ __device__ __forceinline__ void pascal_run(LdsPascal<P, ADJ> &sm, const float2 *
 
   const LaneBoxes<P> lb = lane_boxes<P>(lane);
   const float *zero = bank + B::zero_off;
-  int t = blockIdx.x;
+  // Forward map at p = 12 and 20: workgroups go to the 8 XCDs in turn
+  // (b mod 8), and each XCD's workgroups start on a contiguous run of tiles
+  // (XCD x holds G/8 of them, one more when x < G mod 8, after those of XCDs
+  // 0..x-1), so neighbouring tiles, which share halo boxes, are fetched into
+  // one L2; every workgroup then steps by G, which keeps the runs contiguous
+  // in every round.  At 2^20 points, depth 8, p = 12 this halves the HBM
+  // fetch (21.5 -> 10.2 MB per launch) and runs 0.6% faster.  Elsewhere each
+  // workgroup starts on tile b: at p = 16 this order was 7.7% slower in both
+  // directions, and the adjoint gained nothing measurable at p = 12 and 20.
+  constexpr bool kXcdRuns = !ADJ && (P == 12 || P == 20);
+  int t = int(blockIdx.x);
+  if constexpr (kXcdRuns) {
+    const int b = int(blockIdx.x), G = int(gridDim.x), x = b % 8, q = G / 8, rem = G % 8;
+    t = x * q + (x < rem ? x : rem) + b / 8;
+  }
   TileGeo geo = tile_geo(map, t);
   {
     // this wave's share of the first block, requested behind the scaling
