@@ -89,6 +89,15 @@ struct LdsF32 {
   float red[kRed];
 };
 
+// First tile of this workgroup.  Workgroups go to the 8 XCDs in turn
+// (b mod 8); XCD x's workgroups start on the x-th contiguous run of tiles
+// (G/8 of them, one more when x < G mod 8) and step by G, so in every round
+// the tiles that share halo boxes are fetched into one L2.
+__device__ inline int f32_first_tile() {
+  const int b = int(blockIdx.x), G = int(gridDim.x), x = b % 8, q = G / 8, rem = G % 8;
+  return x * q + (x < rem ? x : rem) + b / 8;
+}
+
 template <int P, bool ADJ, int CX, int CY, int HALF>
 __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__restrict__ X,
                                             const float2 *__restrict__ gbin, float2 *__restrict__ Y,
@@ -176,7 +185,7 @@ __device__ __forceinline__ void m2l_f32_run(LdsF32<P, ADJ> &sm, const float2 *__
   constexpr int kIssueA = 1, kStoreA = (WPC == 1) ? 12 : NI - 3;
   constexpr int kIssueB = (WPC == 1) ? 13 : NI, kStoreB = (WPC == 1) ? 24 : NI;
 
-  int t = blockIdx.x;
+  int t = f32_first_tile();  // the tile the kernel's prologue staged
   TileGeo geo = tile_geo(map, t);
   int cur = 0;
   for (;;) {
@@ -463,7 +472,7 @@ __global__ __launch_bounds__(F32Cfg<P>::kThreads, F32Cfg<P>::kWgPerCu) void m2l_
   if (int(blockIdx.x) >= ntiles) return;
   {
     Prefetch<P, C::kThreads> pf;
-    const TileGeo g = tile_geo(map, blockIdx.x);
+    const TileGeo g = tile_geo(map, f32_first_tile());
     prefetch_issue<P, C::kThreads, ADJ>(pf, g, X, gbin, tid, 0, C::kPf);
     prefetch_store<P, C::kThreads, ADJ>(pf, sm.x[0], sm.gb[0], tid, 0, C::kPf);
     if (ADJ && tid == 0) sm.gb[1][kRegBoxes] = make_float2(0.f, 0.f);
